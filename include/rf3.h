@@ -1,0 +1,155 @@
+/*
+ * rf3.h -- C ABI of librf3, the MI355X (gfx950) implementation of the
+ * recursive-filter horizontal covariance operator of Farina et al.,
+ * "A Revised Scheme to Compute Horizontal Covariances in an Oceanographic
+ * 3D-VAR Assimilation System" (arXiv:1404.5756).
+ *
+ * The library applies V_H = G_y G_x (Sec. 2.2) to temperature/salinity-like
+ * fields on every vertical level, where G_x and G_y are one-dimensional
+ * recursive filters along grid rows and grid columns:
+ *   - the third-order filter (3rd-RF) of Theorem 3.1: a causal sweep
+ *     (eq. "fort") followed by an anti-causal sweep (eq. "bact"), with the
+ *     heuristic initial conditions of Sec. 3.1 (zero state before a line);
+ *   - the first-order filter (1st-RF) of eqs. "proc1-1"/"proc1-2", K times,
+ *     with the coefficients of the Hayden relation (eq. "crucial").
+ * Filter coefficients vary per grid point with sigma = R/dx (Sec. 3.1).
+ * Coasts: each sea run along a line is extended by up to n_img imaginary
+ * sea points (Sec. 1 and Sec. 4 mention them; their definition is this
+ * library's reading: a land point within n_img points of a run joins the
+ * nearer run, ties to the lower index; imaginary points take zero input and
+ * give zero output).
+ *
+ * Conventions (all entry points):
+ *   - Every array argument is a DEVICE pointer.  The caller allocates and
+ *     owns all memory; the library allocates nothing and keeps no state
+ *     between calls.
+ *   - Fields are contiguous [nfields][nlev][ny][nx] (x fastest), FP32 or FP64
+ *     per rf_prec.  in == out is allowed; any other overlap of in and out is
+ *     rejected with RF_E_ARG.
+ *   - Field values at land and imaginary points are ignored (read as 0); the
+ *     output is 0 there.  So the operator is P V_H P with P the sea mask.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every call except
+ *     rf_coeffs only enqueues work on it and returns: it does not
+ *     synchronise and may be captured into a hipGraph.
+ *   - Return value: RF_OK (0) or a negative rf_status.  When a host-side check
+ *     fails nothing has been enqueued.
+ */
+#ifndef RF3_H
+#define RF3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RF_OK = 0,
+    RF_E_ARG = -1,          /* null pointer, bad enum, bad count, overlapping in/out */
+    RF_E_SHAPE = -2,        /* grid sizes out of range or inconsistent with the coefficient block */
+    RF_E_SIGMA = -3,        /* sigma <= 0, NaN or Inf at a sea or imaginary point */
+    RF_E_HIP = -4,          /* a HIP runtime call failed */
+    RF_E_UNSUPPORTED = -5   /* valid request this build does not handle */
+} rf_status;
+
+typedef enum { RF_FP32 = 0, RF_FP64 = 1 } rf_prec;
+
+/* How q enters the Theorem 3.1 polynomials a_{i,k}(q).  beta always uses the
+ * true sigma, (2 pi sigma^2)^(1/4) (1 - sum alpha), so each direction keeps
+ * the DC gain sqrt(2 pi) sigma of Appendix A (eqs. "avanti3", "avanti4").
+ *   LITERAL : q = sigma, exactly as printed in the Theorem.
+ *   VARMATCH: q solves A q^2 + B q = sigma^2, where A q^2 + B q is the
+ *             variance of the causal+anti-causal impulse response
+ *             (A = 2((C1/C0)^2 - 2 C2/C0), B = 2 C1/C0 with C0, C1, C2 the
+ *             constant terms 3.738128, 5.788982, 3.382473 of the Theorem).
+ *   FIT     : q = sigma - 1.3460094 + 1.2463293/(sigma + 0.6031649), the
+ *             least-squares fit of the q that minimises the mass-normalised
+ *             distance of the impulse response to exp(-x^2/(2 sigma^2)). */
+typedef enum { RF_Q_LITERAL = 0, RF_Q_VARMATCH = 1, RF_Q_FIT = 2 } rf_qmode;
+
+typedef struct {
+    int32_t nx, ny, nlev;   /* one level is [ny][nx], x fastest; 1 <= nx, ny <= 65535, nlev >= 1 */
+    int32_t mask_nlev;      /* 1 (one 2-D mask for every level) or nlev */
+    int32_t sigma_nlev;     /* 1 (2-D sigma fields for every level) or nlev */
+    int32_t n_img;          /* imaginary sea points per coast, 0 <= n_img <= 64 */
+    int32_t qmode;          /* rf_qmode */
+    int32_t k1;             /* iteration count K the 1st-RF coefficients are built for (E = K/sigma^2), >= 1 */
+} rf_grid;
+
+/* Size in bytes of the coefficient block rf_coeffs fills for grid g (0 if g is
+ * invalid).  The block holds per-point FP32 and FP64 filter coefficients for
+ * both directions, forward and adjoint forms, the 1st-RF coefficients, and the
+ * per-point coast codes; it is read by every apply call and never written by
+ * them.  Caller-allocated, 256-byte aligned, any device memory. */
+size_t rf_coeffs_bytes(const rf_grid *g);
+
+/* Build the coefficient block (setup; run once per grid, mask and sigma).
+ *   mask    : uint8 [mask_nlev][ny][nx], nonzero = sea.
+ *   sigma_x : double [sigma_nlev][ny][nx], R/dx in grid units (x direction).
+ *   sigma_y : double [sigma_nlev][ny][nx], R/dy in grid units (y direction).
+ *   coef    : rf_coeffs_bytes(g) bytes, written.
+ * Computes the coast segments of every row and column and, in FP64 on the
+ * device, q(sigma), a_{i,0..3}, alpha_{i,k} = a_{i,k}/a_{i,0} and beta_i of
+ * Theorem 3.1 and the 1st-RF alpha_i, beta_i of Sec. 3.1.  sigma must be
+ * positive and finite at every sea and imaginary point (values at other land
+ * points are not read).  This call synchronises `stream` and returns
+ * RF_E_SIGMA if that check fails. */
+int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *sigma_x,
+              const double *sigma_y, void *coef, void *stream);
+
+/* out = G_y G_x in (the 3rd-RF, Theorem 3.1), for each of nfields fields and
+ * each of the first nlev levels (1 <= nlev <= g->nlev).  FP64 follows the
+ * printed recurrence.  FP32 runs an algebraically identical form of it whose
+ * state is the last value and the last two increments, with coefficients
+ * gamma = 1 - sum_k alpha_k, alpha_2 + alpha_3 and alpha_3 formed in FP64. */
+int rf3_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, const void *in,
+                 void *out, int32_t nlev, int32_t nfields, void *stream);
+
+/* out = G_x^T G_y^T in, the exact transpose of rf3_apply_xy (needed for
+ * B = V V^T, Sec. 2.1).  With varying sigma this is a different operator from
+ * rf3_apply_xy. */
+int rf3_adjoint_xy(const rf_grid *g, const void *coef, rf_prec prec, const void *in,
+                   void *out, int32_t nlev, int32_t nfields, void *stream);
+
+/* out = G_y^(K) G_x^(K) in with the 1st-RF: K causal+anti-causal iterations
+ * along x (eqs. "proc1-1", "proc1-2"), then K along y.  K must equal g->k1
+ * (the coefficients depend on K).  Only RF_FP64 is provided: this is the
+ * paper's baseline filter. */
+int rf1_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, int32_t K,
+                 const void *in, void *out, int32_t nlev, int32_t nfields, void *stream);
+
+/* Many independent fields on possibly different grids, processed by one
+ * launch per direction (T and S on every level of several grids; the paper's
+ * global configuration spreads levels over OpenMP threads, Sec. 5.1).
+ * Each item applies rf3_apply_xy (adjoint = 0) or rf3_adjoint_xy
+ * (adjoint = 1) to its own nfields fields over all g->nlev levels of its grid.
+ *
+ * Two steps, so that the apply step can be captured into a hipGraph:
+ *   1. rf3_batch_plan (host only, no HIP call) writes the work list for the
+ *      items into host memory `plan` of rf3_batch_plan_bytes(items, n) bytes;
+ *      the caller copies those bytes to device memory it owns;
+ *   2. rf3_apply_batch reads that device copy (`plan_dev`) and enqueues the
+ *      work.  The same device plan serves any number of calls as long as the
+ *      items (pointers, grids, field counts) are unchanged.
+ * Only RF_FP32.  Items must not overlap each other's outputs. */
+typedef struct {
+    const rf_grid *g;       /* host pointer to the item's grid */
+    const void *coef;       /* device: its coefficient block */
+    const void *in;         /* device: [nfields][g->nlev][ny][nx] FP32 */
+    void *out;              /* device: same shape; may equal in */
+    int32_t nfields;
+} rf_batch_item;
+
+size_t rf3_batch_plan_bytes(const rf_batch_item *items, int32_t n);
+int rf3_batch_plan(const rf_batch_item *items, int32_t n, void *plan, size_t plan_bytes);
+int rf3_apply_batch(const rf_batch_item *items, int32_t n, rf_prec prec, int32_t adjoint,
+                    const void *plan_dev, size_t plan_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *rf_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RF3_H */

@@ -1,0 +1,138 @@
+// C-ABI entry points of librf3: argument checks, then kernel launches on the
+// caller's stream.  No call allocates memory or synchronises, except
+// rf_coeffs (coef.hip), which reports invalid sigma.
+#include <string.h>
+
+#include "rf3_internal.h"
+#include "sweeps.h"
+
+using namespace rf;
+
+namespace {
+
+LineGeom geom(const rf_grid *g, int dir, int nlev, int nfields)
+{
+    LineGeom G;
+    G.n = dir == 0 ? g->nx : g->ny;
+    G.nlines = dir == 0 ? g->ny : g->nx;
+    G.estride = dir == 0 ? 1 : g->nx;
+    G.lstride = dir == 0 ? g->nx : 1;
+    G.plane = (long)g->nx * g->ny;
+    G.nplanes = nlev * nfields;
+    G.nlev = nlev;
+    G.mask_per_lev = g->mask_nlev > 1;
+    G.coef_per_lev = g->sigma_nlev > 1;
+    return G;
+}
+
+int check_apply(const rf_grid *g, const void *coef, int prec, const void *in, const void *out,
+                int nlev, int nfields)
+{
+    if (!g || !coef || !in || !out) return RF_E_ARG;
+    if (prec != RF_FP32 && prec != RF_FP64) return RF_E_ARG;
+    if (!grid_ok(g)) return RF_E_SHAPE;
+    if (nlev < 1 || nlev > g->nlev || nfields < 1) return RF_E_SHAPE;
+    if ((long long)nlev * nfields > (1ll << 30)) return RF_E_SHAPE;
+    if (reinterpret_cast<uintptr_t>(coef) % 256) return RF_E_ARG;
+    const size_t es = prec == RF_FP32 ? 4 : 8;
+    if (reinterpret_cast<uintptr_t>(in) % es || reinterpret_cast<uintptr_t>(out) % es) return RF_E_ARG;
+    if (in != out) {
+        const size_t bytes = (size_t)g->nx * g->ny * (size_t)nlev * nfields * es;
+        const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+        if (a < b + bytes && b < a + bytes) return RF_E_ARG;
+    }
+    return RF_OK;
+}
+
+template <class T>
+const T *tab(const void *coef, uint64_t off)
+{
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(coef) + off);
+}
+
+}  // namespace
+
+// One direction of the 3rd-RF in FP32 (forward when adj is false).
+static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void *coef, int dir,
+                              bool adj, const float *in, float *out, int nlev, int nfields,
+                              hipStream_t st)
+{
+    const LineGeom G = geom(g, dir, nlev, nfields);
+    const float4 *T1 = tab<float4>(coef, adj ? h.off_a32[dir] : h.off_f32[dir]);
+    const float4 *T2 = tab<float4>(coef, adj ? h.off_d32[dir] : h.off_f32[dir]);
+    const uint8_t *code = tab<uint8_t>(coef, h.off_code[dir]);
+    hipError_t e = fast_rf3_f32(in, out, T1, T2, code, G, dir, adj, st);
+    if (e == hipErrorNotSupported) e = seq_rf3_f32(in, out, T1, T2, code, G, adj, st);
+    return e;
+}
+
+static int rf3_run(const rf_grid *g, const void *coef, rf_prec prec, const void *in, void *out,
+                   int32_t nlev, int32_t nfields, void *stream, bool adj)
+{
+    const int rc = check_apply(g, coef, prec, in, out, nlev, nfields);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const BlockHeader h = layout(g);
+    // forward: x then y;  adjoint: y then x.  The second pass runs in place on out.
+    const int d0 = adj ? 1 : 0, d1 = adj ? 0 : 1;
+    hipError_t e;
+    if (prec == RF_FP32) {
+        e = rf3_dir_f32(g, h, coef, d0, adj, (const float *)in, (float *)out, nlev, nfields, st);
+        if (e == hipSuccess)
+            e = rf3_dir_f32(g, h, coef, d1, adj, (const float *)out, (float *)out, nlev, nfields, st);
+    } else {
+        e = seq_rf3_f64((const double *)in, (double *)out, tab<double4>(coef, h.off_f64[d0]),
+                        tab<uint8_t>(coef, h.off_code[d0]), geom(g, d0, nlev, nfields), adj, st);
+        if (e == hipSuccess)
+            e = seq_rf3_f64((const double *)out, (double *)out, tab<double4>(coef, h.off_f64[d1]),
+                            tab<uint8_t>(coef, h.off_code[d1]), geom(g, d1, nlev, nfields), adj, st);
+    }
+    return e == hipSuccess ? RF_OK : RF_E_HIP;
+}
+
+extern "C" int rf3_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, const void *in,
+                            void *out, int32_t nlev, int32_t nfields, void *stream)
+{
+    return rf3_run(g, coef, prec, in, out, nlev, nfields, stream, false);
+}
+
+extern "C" int rf3_adjoint_xy(const rf_grid *g, const void *coef, rf_prec prec, const void *in,
+                              void *out, int32_t nlev, int32_t nfields, void *stream)
+{
+    return rf3_run(g, coef, prec, in, out, nlev, nfields, stream, true);
+}
+
+extern "C" int rf1_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, int32_t K,
+                            const void *in, void *out, int32_t nlev, int32_t nfields, void *stream)
+{
+    const int rc = check_apply(g, coef, prec, in, out, nlev, nfields);
+    if (rc) return rc;
+    if (K != g->k1 || K < 1) return RF_E_ARG;
+    if (prec != RF_FP64) return RF_E_UNSUPPORTED;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const BlockHeader h = layout(g);
+    hipError_t e = hipSuccess;
+    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+        const LineGeom G = geom(g, dir, nlev, nfields);
+        const double2 *C = tab<double2>(coef, h.off_r1[dir]);
+        const uint8_t *code = tab<uint8_t>(coef, h.off_code[dir]);
+        for (int k = 0; k < K && e == hipSuccess; ++k) {
+            const double *src = (dir == 0 && k == 0) ? (const double *)in : (const double *)out;
+            e = seq_rf1_f64(src, (double *)out, C, code, G, k == 0, k == K - 1, st);
+        }
+    }
+    return e == hipSuccess ? RF_OK : RF_E_HIP;
+}
+
+extern "C" const char *rf_strerror(int status)
+{
+    switch (status) {
+    case RF_OK: return "success";
+    case RF_E_ARG: return "invalid argument (null pointer, bad enum or count, misaligned or overlapping buffers)";
+    case RF_E_SHAPE: return "invalid grid or level/field count";
+    case RF_E_SIGMA: return "sigma not positive and finite at a sea or imaginary point";
+    case RF_E_HIP: return "HIP runtime error";
+    case RF_E_UNSUPPORTED: return "request not supported by this build";
+    default: return "unknown status";
+    }
+}

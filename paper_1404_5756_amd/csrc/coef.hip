@@ -1,0 +1,253 @@
+// Setup of the coefficient block: coast codes of every row and column, and the
+// per-point filter coefficients of both directions, computed in FP64 on the GPU.
+//
+//   3rd-RF (Theorem 3.1, Sec. 3.1):
+//     a_{i,0} = 3.738128 + 5.788982 q + 3.382473 q^2 + q^3
+//     a_{i,1} = 5.788982 q + 6.764946 q^2 + 3 q^3
+//     a_{i,2} = -3.382473 q^2 - 3 q^3
+//     a_{i,3} = q^3
+//     alpha_{i,k} = a_{i,k}/a_{i,0},  beta_i = (2 pi sigma^2)^(1/4) (1 - sum_k alpha_{i,k})
+//   with q = q(sigma) per rf_qmode.
+//   1st-RF (Hayden relation, eq. "crucial"): E = K/sigma^2,
+//     alpha_i = 1 + E - sqrt(E(E+2)),  beta_i = -E + sqrt(E(E+2)).
+//
+// The FP32 sweeps use the same recurrence rewritten around the small
+// quantities gamma = 1 - sum_k alpha_k (= 3.738128/a_0 exactly, since the
+// a_{i,k} sum to a_{i,0} - 3.738128), c2 = alpha_2 + alpha_3, c3 = alpha_3;
+// they are formed here in FP64 and rounded once.
+#include <math.h>
+
+#include "rf3_internal.h"
+
+namespace rf {
+
+__device__ inline double qmap(int mode, double sigma)
+{
+    if (mode == RF_Q_LITERAL) return sigma;
+    if (mode == RF_Q_VARMATCH) {
+        // variance of the causal+anti-causal pair on an infinite line:
+        //   A q^2 + B q,  A = 2((C1/C0)^2 - 2 C2/C0),  B = 2 C1/C0
+        const double C0 = 3.738128, C1 = 5.788982, C2 = 3.382473;
+        const double r = C1 / C0;
+        const double A = 2.0 * (r * r - 2.0 * C2 / C0), B = 2.0 * r;
+        return (-B + sqrt(B * B + 4.0 * A * sigma * sigma)) / (2.0 * A);
+    }
+    return sigma - 1.3460094 + 1.2463293 / (sigma + 0.6031649);   // RF_Q_FIT
+}
+
+__device__ inline bool sigma_ok(double s) { return s > 0.0 && s < INFINITY; }
+
+struct Coef3 {
+    double al1, al2, al3, beta, gam, c2, c3, beta_g;
+};
+
+__device__ inline Coef3 coef3(int mode, double sigma)
+{
+    Coef3 c;
+    const double q = qmap(mode, sigma), q2 = q * q, q3 = q2 * q;
+    const double a0 = 3.738128 + 5.788982 * q + 3.382473 * q2 + q3;
+    const double a1 = 5.788982 * q + 6.764946 * q2 + 3.0 * q3;
+    const double a2 = -3.382473 * q2 - 3.0 * q3;
+    const double a3 = q3;
+    c.al1 = a1 / a0;
+    c.al2 = a2 / a0;
+    c.al3 = a3 / a0;
+    const double f = sqrt(sqrt(2.0 * M_PI * sigma * sigma));     // (2 pi sigma^2)^(1/4)
+    c.beta = f * (1.0 - (c.al1 + c.al2 + c.al3));
+    c.gam = 3.738128 / a0;
+    c.c2 = (a2 + a3) / a0;
+    c.c3 = a3 / a0;
+    c.beta_g = f * c.gam;
+    return c;
+}
+
+// kind of point i of a line: 0 outside every segment, 1 sea, 2 imaginary point
+// of the run before it, 3 imaginary point of the run after it.
+__device__ inline int classify(const uint8_t *m, long es, int n, int i, int n_img)
+{
+    if (m[(long)i * es]) return 1;
+    int dl = n_img + 1, dr = n_img + 1;
+    for (int k = 1; k <= n_img && i - k >= 0; ++k)
+        if (m[(long)(i - k) * es]) { dl = k; break; }
+    for (int k = 1; k <= n_img && i + k < n; ++k)
+        if (m[(long)(i + k) * es]) { dr = k; break; }
+    if (dl > n_img && dr > n_img) return 0;
+    return dl <= dr ? 2 : 3;
+}
+
+// One thread per (mask level, y, x); writes the codes of both directions.
+__global__ void k_seg(const uint8_t *__restrict__ mask, uint8_t *__restrict__ code_x,
+                      uint8_t *__restrict__ code_y, int nx, int ny, int nl, int n_img)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long plane = (long)nx * ny;
+    if (t >= plane * nl) return;
+    const int lev = (int)(t / plane);
+    const long r = t % plane;
+    const int y = (int)(r / nx), x = (int)(r % nx);
+    const uint8_t *mp = mask + lev * plane;
+    for (int d = 0; d < 2; ++d) {
+        const int n = d == 0 ? nx : ny;
+        const int i = d == 0 ? x : y;
+        const long es = d == 0 ? 1 : nx;
+        const uint8_t *line = d == 0 ? mp + (long)y * nx : mp + x;
+        const int k = classify(line, es, n, i, n_img);
+        const int kp = i > 0 ? classify(line, es, n, i - 1, n_img) : 0;
+        const int kn = i < n - 1 ? classify(line, es, n, i + 1, n_img) : 0;
+        uint8_t c = 0;
+        if (k == 1) c |= CODE_SEA;
+        if (k != 0) {
+            c |= CODE_ACTIVE;
+            // a new segment starts where the previous point is outside every
+            // segment or is an imaginary point of the run before a gap whose
+            // other side (this point) belongs to the next run
+            const bool start = (i == 0) || kp == 0 || (kp == 2 && (k == 3 || k == 1));
+            const bool end = (i == n - 1) || kn == 0 || (k == 2 && (kn == 3 || kn == 1));
+            if (start) c |= CODE_FRESET;
+            if (end) c |= CODE_BRESET;
+        } else {
+            c |= CODE_FRESET | CODE_BRESET;
+        }
+        (d == 0 ? code_x : code_y)[t] = c;
+    }
+}
+
+// alpha_{., k} of the point `off` steps away along the line, 0 outside the line
+// or where sigma is not usable (such points never reach a used state term).
+__device__ inline double alpha_at(const double *sig, long es, int n, int i, int off, int k, int mode)
+{
+    const int j = i + off;
+    if (j < 0 || j >= n) return 0.0;
+    const double s = sig[(long)j * es];
+    if (!sigma_ok(s)) return 0.0;
+    const Coef3 c = coef3(mode, s);
+    return k == 1 ? c.al1 : (k == 2 ? c.al2 : c.al3);
+}
+
+// One thread per (sigma level, y, x): coefficient tables of both directions.
+__global__ void k_coef(const double *__restrict__ sx, const double *__restrict__ sy,
+                       const uint8_t *__restrict__ code_x, const uint8_t *__restrict__ code_y,
+                       char *__restrict__ blk, BlockHeader h)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = h.g.nx, ny = h.g.ny;
+    const long plane = (long)nx * ny;
+    if (t >= (long)h.npts_c) return;
+    const int lev = (int)(t / plane);
+    const long r = t % plane;
+    const int y = (int)(r / nx), x = (int)(r % nx);
+    const int mode = h.g.qmode;
+    for (int d = 0; d < 2; ++d) {
+        const double *sig = (d == 0 ? sx : sy) + lev * plane;
+        const uint8_t *code = d == 0 ? code_x : code_y;
+        const double s = sig[r];
+        // is the point inside a segment on some level that uses this sigma plane?
+        bool used = false;
+        if (h.g.mask_nlev == h.g.sigma_nlev) {
+            used = code[t] & CODE_ACTIVE;
+        } else if (h.g.mask_nlev == 1) {
+            used = code[r] & CODE_ACTIVE;
+        } else {
+            for (int l = 0; l < h.g.mask_nlev && !used; ++l) used = code[l * plane + r] & CODE_ACTIVE;
+        }
+        float4 f = make_float4(0.f, 0.f, 0.f, 0.f), a = f, b = f;
+        double4 f64 = make_double4(0.0, 0.0, 0.0, 0.0);
+        double2 r1 = make_double2(0.0, 0.0);
+        if (sigma_ok(s)) {
+            const Coef3 c = coef3(mode, s);
+            f = make_float4((float)c.beta_g, (float)c.gam, (float)c.c2, (float)c.c3);
+            f64 = make_double4(c.beta, c.al1, c.al2, c.al3);
+            // adjoint: source-indexed alphas of the neighbours along the line
+            const int n = d == 0 ? nx : ny, i = d == 0 ? x : y;
+            const long es = d == 0 ? 1 : nx;
+            const double *line = d == 0 ? sig + (long)y * nx : sig + x;
+            const double A1 = alpha_at(line, es, n, i, -1, 1, mode);
+            const double A2 = alpha_at(line, es, n, i, -2, 2, mode);
+            const double A3 = alpha_at(line, es, n, i, -3, 3, mode);
+            a = make_float4((float)c.beta_g, (float)(1.0 - A1 - A2 - A3), (float)(A2 + A3), (float)A3);
+            const double D1 = alpha_at(line, es, n, i, 1, 1, mode);
+            const double D2 = alpha_at(line, es, n, i, 2, 2, mode);
+            const double D3 = alpha_at(line, es, n, i, 3, 3, mode);
+            b = make_float4((float)c.beta_g, (float)(1.0 - D1 - D2 - D3), (float)(D2 + D3), (float)D3);
+            const double E = (double)h.g.k1 / (s * s);
+            const double rt = sqrt(E * (E + 2.0));
+            r1 = make_double2(1.0 + E - rt, -E + rt);
+        } else if (used) {
+            atomicAdd(&reinterpret_cast<BlockHeader *>(blk)->sigma_error, 1);
+        }
+        reinterpret_cast<float4 *>(blk + h.off_f32[d])[t] = f;
+        reinterpret_cast<float4 *>(blk + h.off_a32[d])[t] = a;
+        reinterpret_cast<float4 *>(blk + h.off_d32[d])[t] = b;
+        reinterpret_cast<double4 *>(blk + h.off_f64[d])[t] = f64;
+        reinterpret_cast<double2 *>(blk + h.off_r1[d])[t] = r1;
+    }
+}
+
+bool grid_ok(const rf_grid *g)
+{
+    if (!g) return false;
+    if (g->nx < 1 || g->ny < 1 || g->nx > 65535 || g->ny > 65535 || g->nlev < 1) return false;
+    if (g->mask_nlev != 1 && g->mask_nlev != g->nlev) return false;
+    if (g->sigma_nlev != 1 && g->sigma_nlev != g->nlev) return false;
+    if (g->n_img < 0 || g->n_img > 64) return false;
+    if (g->qmode < RF_Q_LITERAL || g->qmode > RF_Q_FIT) return false;
+    if (g->k1 < 1) return false;
+    return true;
+}
+
+BlockHeader layout(const rf_grid *g)
+{
+    BlockHeader h{};
+    h.magic = kMagic;
+    h.version = kVersion;
+    h.g = *g;
+    const size_t plane = (size_t)g->nx * g->ny;
+    h.npts_c = plane * g->sigma_nlev;
+    h.npts_m = plane * g->mask_nlev;
+    size_t off = 256;
+    for (int d = 0; d < 2; ++d) {
+        h.off_f32[d] = off; off = align256(off + 16 * h.npts_c);
+        h.off_a32[d] = off; off = align256(off + 16 * h.npts_c);
+        h.off_d32[d] = off; off = align256(off + 16 * h.npts_c);
+        h.off_f64[d] = off; off = align256(off + 32 * h.npts_c);
+        h.off_r1[d] = off;  off = align256(off + 16 * h.npts_c);
+    }
+    for (int d = 0; d < 2; ++d) { h.off_code[d] = off; off = align256(off + h.npts_m); }
+    h.total_bytes = off;
+    return h;
+}
+
+}  // namespace rf
+
+using namespace rf;
+
+extern "C" size_t rf_coeffs_bytes(const rf_grid *g)
+{
+    if (!grid_ok(g)) return 0;
+    return layout(g).total_bytes;
+}
+
+extern "C" int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *sigma_x,
+                         const double *sigma_y, void *coef, void *stream)
+{
+    if (!g || !mask || !sigma_x || !sigma_y || !coef) return RF_E_ARG;
+    if (!grid_ok(g)) return RF_E_SHAPE;
+    if (reinterpret_cast<uintptr_t>(coef) % 256) return RF_E_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    BlockHeader h = layout(g);
+    char *blk = reinterpret_cast<char *>(coef);
+    if (hipMemcpyAsync(blk, &h, sizeof(h), hipMemcpyHostToDevice, st) != hipSuccess) return RF_E_HIP;
+    const long nm = (long)h.npts_m, nc = (long)h.npts_c;
+    k_seg<<<(unsigned)((nm + 255) / 256), 256, 0, st>>>(mask, (uint8_t *)(blk + h.off_code[0]),
+                                                      (uint8_t *)(blk + h.off_code[1]), g->nx, g->ny,
+                                                      g->mask_nlev, g->n_img);
+    if (hipGetLastError() != hipSuccess) return RF_E_HIP;
+    k_coef<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(sigma_x, sigma_y, (const uint8_t *)(blk + h.off_code[0]),
+                                                       (const uint8_t *)(blk + h.off_code[1]), blk, h);
+    if (hipGetLastError() != hipSuccess) return RF_E_HIP;
+    int32_t err = 0;
+    if (hipMemcpyAsync(&err, blk + offsetof(BlockHeader, sigma_error), sizeof(err), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return RF_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return RF_E_HIP;
+    return err ? RF_E_SIGMA : RF_OK;
+}

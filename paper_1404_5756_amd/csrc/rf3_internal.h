@@ -1,0 +1,71 @@
+// Internal layout of the coefficient block and helpers shared by the librf3
+// sources.  Not part of the public ABI (include/rf3.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rf3.h"
+
+namespace rf {
+
+constexpr uint32_t kMagic = 0x52463321u;   // "RF3!"
+constexpr uint32_t kVersion = 1;
+
+// Per-point coast code bits (one byte per point and direction).
+enum : uint8_t {
+    CODE_SEA = 1,      // sea point: input read, output written
+    CODE_FRESET = 2,   // state is zero before this point in the ascending sweep
+                       // (first point of a segment, or a point outside every segment)
+    CODE_BRESET = 4,   // state is zero before this point in the descending sweep
+                       // (last point of a segment, or outside every segment)
+    CODE_ACTIVE = 8,   // sea or imaginary point (inside a segment)
+};
+
+// Tables per direction (0 = x, 1 = y).  Element index of every per-point table
+// is (level * ny + y) * nx + x, where level is the sigma level for coefficient
+// tables and the mask level for code tables.
+struct BlockHeader {
+    uint32_t magic, version;
+    rf_grid g;
+    uint64_t npts_c;          // sigma_nlev * ny * nx
+    uint64_t npts_m;          // mask_nlev * ny * nx
+    // FP32, forward:  (beta, gamma, c2, c3) with gamma = 1 - (a1+a2+a3), c2 = a2+a3, c3 = a3
+    uint64_t off_f32[2];
+    // FP32, adjoint ascending sweep: (beta, Ga, C2a, C3a) built from alpha_{j-k,k}
+    uint64_t off_a32[2];
+    // FP32, adjoint descending sweep: (beta, Gd, C2d, C3d) built from alpha_{j+k,k}
+    uint64_t off_d32[2];
+    // FP64, printed form: (beta, alpha1, alpha2, alpha3)
+    uint64_t off_f64[2];
+    // FP64 1st-RF: (alpha, beta)
+    uint64_t off_r1[2];
+    // uint8 coast codes
+    uint64_t off_code[2];
+    uint64_t total_bytes;
+    int32_t sigma_error;      // device-written: number of active points with invalid sigma
+    int32_t pad[3];
+};
+static_assert(sizeof(BlockHeader) <= 256, "header must fit in 256 bytes");
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Geometry of one direction's lines inside a [nplanes][ny][nx] field stack.
+struct LineGeom {
+    int n;            // points per line
+    int nlines;       // lines per plane (level)
+    long estride;     // element stride along a line
+    long lstride;     // stride between neighbouring lines
+    long plane;       // nx * ny
+    int nplanes;      // nfields * nlev planes to process
+    int nlev;         // levels per field (plane index % nlev = level)
+    int mask_per_lev; // 1: code tables have one plane per level; 0: a single 2-D plane
+    int coef_per_lev; // same for coefficient tables
+};
+
+__host__ __device__ inline long plane_offset(const LineGeom &G, int pl, int per_lev)
+{
+    return per_lev ? (long)(pl % G.nlev) * G.plane : 0;
+}
+
+}  // namespace rf

@@ -1,0 +1,225 @@
+// Line-sequential sweep kernels: one lane runs one whole line.  They serve the
+// FP64 path (printed recurrence, same order of operations as the paper), the
+// 1st-RF baseline, and any FP32 shape the tiled kernels do not cover.
+//
+// The causal sweep writes its result into `out` and the anti-causal sweep
+// reads it back in reverse, so one line is processed entirely by one lane.
+#include "rf3_internal.h"
+#include "sweeps.h"
+
+namespace rf {
+
+__device__ inline long line_base(const LineGeom &G, long t, int &pl)
+{
+    pl = (int)(t / G.nlines);
+    const int ln = (int)(t % G.nlines);
+    return (long)ln * G.lstride;
+}
+
+// ---------------------------------------------------------------- FP32
+// Third-order recurrence of eqs. "fort"/"bact" written on the state
+// (p_{i-1}, d1 = p_{i-1}-p_{i-2}, d2 = p_{i-2}-p_{i-3}):
+//   t_i = g_i s_i - gamma_i p_{i-1} - c2_i d1 - c3_i d2,  p_i = p_{i-1} + t_i,
+// which equals p_i = beta_i s_i + sum_k alpha_{i,k} p_{i-k} exactly in real
+// arithmetic (gamma = 1 - sum alpha, c2 = alpha2 + alpha3, c3 = alpha3) and
+// keeps the small increment t_i as state, so FP32 rounding of p does not feed
+// back through the near-unit-root recursion.
+template <bool ADJ>
+__global__ void k_rf3_seq_f32(const float *in, float *out, const float4 *__restrict__ T1,
+                              const float4 *__restrict__ T2, const uint8_t *__restrict__ code,
+                              LineGeom G)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)G.nplanes * G.nlines) return;
+    int pl;
+    const long lb = line_base(G, t, pl);
+    const long fb = (long)pl * G.plane + lb;
+    const long cb = plane_offset(G, pl, G.coef_per_lev) + lb;
+    const long mb = plane_offset(G, pl, G.mask_per_lev) + lb;
+    float p1 = 0.f, d1 = 0.f, d2 = 0.f;
+    for (int i = 0; i < G.n; ++i) {
+        const long e = (long)i * G.estride;
+        const uint8_t c = code[mb + e];
+        if (c & CODE_FRESET) { p1 = 0.f; d1 = 0.f; d2 = 0.f; }
+        const float4 k = T1[cb + e];
+        const float s = (c & CODE_SEA) ? in[fb + e] : 0.f;
+        const float g = ADJ ? 1.f : k.x;
+        const float tt = fmaf(-k.w, d2, fmaf(-k.z, d1, fmaf(-k.y, p1, g * s)));
+        const float p = p1 + tt;
+        d2 = d1; d1 = tt; p1 = p;
+        out[fb + e] = p;
+    }
+    p1 = 0.f; d1 = 0.f; d2 = 0.f;
+    for (int i = G.n - 1; i >= 0; --i) {
+        const long e = (long)i * G.estride;
+        const uint8_t c = code[mb + e];
+        if (c & CODE_BRESET) { p1 = 0.f; d1 = 0.f; d2 = 0.f; }
+        const float4 k = T2[cb + e];
+        const float v = out[fb + e];
+        const float tt = fmaf(-k.w, d2, fmaf(-k.z, d1, fmaf(-k.y, p1, k.x * v)));
+        const float p = p1 + tt;
+        d2 = d1; d1 = tt; p1 = p;
+        out[fb + e] = (c & CODE_SEA) ? (ADJ ? k.x * p : p) : 0.f;
+    }
+}
+
+// ---------------------------------------------------------------- FP64
+// Printed form: p_i = beta_i s_i + alpha_{i,1} p_{i-1} + alpha_{i,2} p_{i-2} + alpha_{i,3} p_{i-3}
+// (eq. "fort"), o_i = beta_i p_i + sum_k alpha_{i,k} o_{i+k} (eq. "bact").
+__global__ void k_rf3_seq_f64(const double *in, double *out, const double4 *__restrict__ C,
+                              const uint8_t *__restrict__ code, LineGeom G)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)G.nplanes * G.nlines) return;
+    int pl;
+    const long lb = line_base(G, t, pl);
+    const long fb = (long)pl * G.plane + lb;
+    const long cb = plane_offset(G, pl, G.coef_per_lev) + lb;
+    const long mb = plane_offset(G, pl, G.mask_per_lev) + lb;
+    double p1 = 0, p2 = 0, p3 = 0;
+    for (int i = 0; i < G.n; ++i) {
+        const long e = (long)i * G.estride;
+        const uint8_t c = code[mb + e];
+        if (c & CODE_FRESET) { p1 = 0; p2 = 0; p3 = 0; }
+        const double4 k = C[cb + e];
+        const double s = (c & CODE_SEA) ? in[fb + e] : 0.0;
+        double v = k.x * s;
+        v += k.y * p1;
+        v += k.z * p2;
+        v += k.w * p3;
+        p3 = p2; p2 = p1; p1 = v;
+        out[fb + e] = v;
+    }
+    p1 = 0; p2 = 0; p3 = 0;
+    for (int i = G.n - 1; i >= 0; --i) {
+        const long e = (long)i * G.estride;
+        const uint8_t c = code[mb + e];
+        if (c & CODE_BRESET) { p1 = 0; p2 = 0; p3 = 0; }
+        const double4 k = C[cb + e];
+        double v = k.x * out[fb + e];
+        v += k.y * p1;
+        v += k.z * p2;
+        v += k.w * p3;
+        p3 = p2; p2 = p1; p1 = v;
+        out[fb + e] = (c & CODE_SEA) ? v : 0.0;
+    }
+}
+
+// Transpose of k_rf3_seq_f64 (G^T = D_beta L^-T D_beta U^-T):
+//   z_j = y_j + alpha_{j-1,1} z_{j-1} + alpha_{j-2,2} z_{j-2} + alpha_{j-3,3} z_{j-3}
+//   u_j = beta_j z_j + alpha_{j+1,1} u_{j+1} + alpha_{j+2,2} u_{j+2} + alpha_{j+3,3} u_{j+3}
+//   out_j = beta_j u_j
+__global__ void k_rf3_seq_f64_adj(const double *in, double *out, const double4 *__restrict__ C,
+                                  const uint8_t *__restrict__ code, LineGeom G)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)G.nplanes * G.nlines) return;
+    int pl;
+    const long lb = line_base(G, t, pl);
+    const long fb = (long)pl * G.plane + lb;
+    const long cb = plane_offset(G, pl, G.coef_per_lev) + lb;
+    const long mb = plane_offset(G, pl, G.mask_per_lev) + lb;
+    double z1 = 0, z2 = 0, z3 = 0;
+    double4 k1 = make_double4(0, 0, 0, 0), k2 = k1, k3 = k1;   // coefficients of j-1, j-2, j-3
+    for (int i = 0; i < G.n; ++i) {
+        const long e = (long)i * G.estride;
+        const uint8_t c = code[mb + e];
+        if (c & CODE_FRESET) { z1 = 0; z2 = 0; z3 = 0; }
+        const double4 k = C[cb + e];
+        double v = (c & CODE_SEA) ? in[fb + e] : 0.0;
+        v += k1.y * z1;
+        v += k2.z * z2;
+        v += k3.w * z3;
+        z3 = z2; z2 = z1; z1 = v;
+        k3 = k2; k2 = k1; k1 = k;
+        out[fb + e] = k.x * v;
+    }
+    z1 = 0; z2 = 0; z3 = 0;
+    k1 = make_double4(0, 0, 0, 0); k2 = k1; k3 = k1;              // coefficients of j+1, j+2, j+3
+    for (int i = G.n - 1; i >= 0; --i) {
+        const long e = (long)i * G.estride;
+        const uint8_t c = code[mb + e];
+        if (c & CODE_BRESET) { z1 = 0; z2 = 0; z3 = 0; }
+        const double4 k = C[cb + e];
+        double v = out[fb + e];
+        v += k1.y * z1;
+        v += k2.z * z2;
+        v += k3.w * z3;
+        z3 = z2; z2 = z1; z1 = v;
+        k3 = k2; k2 = k1; k1 = k;
+        out[fb + e] = (c & CODE_SEA) ? k.x * v : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- 1st-RF
+// One iteration of eqs. "proc1-1"/"proc1-2" on every line: p_i = beta_i s_i +
+// alpha_i p_{i-1} ascending, s_i = beta_i p_i + alpha_i s_{i+1} descending.
+// FIRST masks the input to sea points; LAST zeroes non-sea outputs (values at
+// imaginary points are carried from one iteration to the next).
+template <bool FIRST, bool LAST>
+__global__ void k_rf1_seq_f64(const double *in, double *out, const double2 *__restrict__ C,
+                              const uint8_t *__restrict__ code, LineGeom G)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)G.nplanes * G.nlines) return;
+    int pl;
+    const long lb = line_base(G, t, pl);
+    const long fb = (long)pl * G.plane + lb;
+    const long cb = plane_offset(G, pl, G.coef_per_lev) + lb;
+    const long mb = plane_offset(G, pl, G.mask_per_lev) + lb;
+    double p = 0;
+    for (int i = 0; i < G.n; ++i) {
+        const long e = (long)i * G.estride;
+        const uint8_t c = code[mb + e];
+        if (c & CODE_FRESET) p = 0;
+        const double2 k = C[cb + e];
+        double s = in[fb + e];
+        if (FIRST && !(c & CODE_SEA)) s = 0.0;
+        p = k.y * s + k.x * p;
+        out[fb + e] = p;
+    }
+    p = 0;
+    for (int i = G.n - 1; i >= 0; --i) {
+        const long e = (long)i * G.estride;
+        const uint8_t c = code[mb + e];
+        if (c & CODE_BRESET) p = 0;
+        const double2 k = C[cb + e];
+        p = k.y * out[fb + e] + k.x * p;
+        out[fb + e] = (LAST && !(c & CODE_SEA)) ? 0.0 : p;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned nblocks(const LineGeom &G, int bs)
+{
+    return (unsigned)(((long)G.nplanes * G.nlines + bs - 1) / bs);
+}
+
+hipError_t seq_rf3_f32(const float *in, float *out, const float4 *T1, const float4 *T2,
+                       const uint8_t *code, const LineGeom &G, bool adj, hipStream_t st)
+{
+    if (adj) k_rf3_seq_f32<true><<<nblocks(G, 256), 256, 0, st>>>(in, out, T1, T2, code, G);
+    else k_rf3_seq_f32<false><<<nblocks(G, 256), 256, 0, st>>>(in, out, T1, T2, code, G);
+    return hipGetLastError();
+}
+
+hipError_t seq_rf3_f64(const double *in, double *out, const double4 *C, const uint8_t *code,
+                       const LineGeom &G, bool adj, hipStream_t st)
+{
+    if (adj) k_rf3_seq_f64_adj<<<nblocks(G, 256), 256, 0, st>>>(in, out, C, code, G);
+    else k_rf3_seq_f64<<<nblocks(G, 256), 256, 0, st>>>(in, out, C, code, G);
+    return hipGetLastError();
+}
+
+hipError_t seq_rf1_f64(const double *in, double *out, const double2 *C, const uint8_t *code,
+                       const LineGeom &G, bool first, bool last, hipStream_t st)
+{
+    const unsigned nb = nblocks(G, 256);
+    if (first && last) k_rf1_seq_f64<true, true><<<nb, 256, 0, st>>>(in, out, C, code, G);
+    else if (first) k_rf1_seq_f64<true, false><<<nb, 256, 0, st>>>(in, out, C, code, G);
+    else if (last) k_rf1_seq_f64<false, true><<<nb, 256, 0, st>>>(in, out, C, code, G);
+    else k_rf1_seq_f64<false, false><<<nb, 256, 0, st>>>(in, out, C, code, G);
+    return hipGetLastError();
+}
+
+}  // namespace rf

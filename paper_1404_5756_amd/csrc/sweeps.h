@@ -1,0 +1,24 @@
+// Kernel launchers shared between the librf3 sources.
+#pragma once
+#include "rf3_internal.h"
+
+namespace rf {
+
+bool grid_ok(const rf_grid *g);
+BlockHeader layout(const rf_grid *g);
+
+// line-sequential kernels (sweep_seq.hip)
+hipError_t seq_rf3_f32(const float *in, float *out, const float4 *T1, const float4 *T2,
+                       const uint8_t *code, const LineGeom &G, bool adj, hipStream_t st);
+hipError_t seq_rf3_f64(const double *in, double *out, const double4 *C, const uint8_t *code,
+                       const LineGeom &G, bool adj, hipStream_t st);
+hipError_t seq_rf1_f64(const double *in, double *out, const double2 *C, const uint8_t *code,
+                       const LineGeom &G, bool first, bool last, hipStream_t st);
+
+}  // namespace rf
+
+namespace rf {
+// tiled FP32 kernels (sweep_fast.hip); hipErrorNotSupported when the shape is not covered
+hipError_t fast_rf3_f32(const float *in, float *out, const float4 *T1, const float4 *T2,
+                        const uint8_t *code, const LineGeom &G, int dir, bool adj, hipStream_t st);
+}  // namespace rf

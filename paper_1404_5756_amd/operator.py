@@ -1,0 +1,88 @@
+"""V_H = G_y G_x on a GPU-resident grid: holds the grid and its coefficient block.
+
+Thin object wrapper over the C ABI (rf3.py); every computation is a librf3 call.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import rf3
+
+
+def _dev_tensor(a, dtype, device):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+
+class HorizontalCovariance:
+    """Operator V_H (3rd-RF) with its adjoint and the 1st-RF baseline on one grid.
+
+    mask: [mask_nlev][ny][nx] (nonzero = sea); sigma_x, sigma_y: [sigma_nlev][ny][nx] in grid units.
+    """
+
+    def __init__(self, mask, sigma_x, sigma_y, nlev, n_img=0, qmode="literal", k1=5, device="cuda",
+                 stream=None):
+        mask = np.asarray(mask.cpu() if isinstance(mask, torch.Tensor) else mask)
+        if mask.ndim == 2:
+            mask = mask[None]
+        sx = sigma_x if isinstance(sigma_x, torch.Tensor) else np.asarray(sigma_x, np.float64)
+        sy = sigma_y if isinstance(sigma_y, torch.Tensor) else np.asarray(sigma_y, np.float64)
+        if sx.ndim == 2:
+            sx = sx[None]
+        if sy.ndim == 2:
+            sy = sy[None]
+        ny, nx = mask.shape[1:]
+        self.device = torch.device(device)
+        self.grid = rf3.make_grid(nx, ny, nlev, mask.shape[0], sx.shape[0], n_img, qmode, k1)
+        nbytes = rf3.rf_coeffs_bytes(self.grid)
+        if nbytes == 0:
+            raise rf3.RFError(rf3.RF_E_SHAPE, "rf_coeffs_bytes")
+        # 256-byte aligned: torch's caching allocator returns 512-byte aligned blocks
+        self.coef = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        m = _dev_tensor((mask != 0).astype(np.uint8), torch.uint8, self.device)
+        sxd = _dev_tensor(sx, torch.float64, self.device)
+        syd = _dev_tensor(sy, torch.float64, self.device)
+        rf3.rf_coeffs(self.grid, m, sxd, syd, self.coef, stream)
+        self.nx, self.ny, self.nlev = nx, ny, nlev
+
+    # fields: [nfields][nlev][ny][nx] (or [nlev][ny][nx] / [ny][nx])
+    def _shape(self, x):
+        if x.dim() == 2:
+            return 1, 1
+        if x.dim() == 3:
+            return 1, x.shape[0]
+        return x.shape[0], x.shape[1]
+
+    def _prec(self, x):
+        if x.dtype == torch.float32:
+            return rf3.RF_FP32
+        if x.dtype == torch.float64:
+            return rf3.RF_FP64
+        raise TypeError(f"fields must be float32 or float64, got {x.dtype}")
+
+    def apply(self, x, out=None, stream=None):
+        """out = G_y G_x x."""
+        x = x.contiguous()
+        out = torch.empty_like(x) if out is None else out
+        nf, nl = self._shape(x)
+        rf3.rf3_apply_xy(self.grid, self.coef, self._prec(x), x, out, nl, nf, stream)
+        return out
+
+    def adjoint(self, x, out=None, stream=None):
+        """out = G_x^T G_y^T x."""
+        x = x.contiguous()
+        out = torch.empty_like(x) if out is None else out
+        nf, nl = self._shape(x)
+        rf3.rf3_adjoint_xy(self.grid, self.coef, self._prec(x), x, out, nl, nf, stream)
+        return out
+
+    def rf1(self, x, K=None, out=None, stream=None):
+        """1st-RF baseline, K iterations per direction (FP64)."""
+        x = x.contiguous()
+        out = torch.empty_like(x) if out is None else out
+        nf, nl = self._shape(x)
+        rf3.rf1_apply_xy(self.grid, self.coef, self._prec(x), self.grid.k1 if K is None else K, x, out,
+                         nl, nf, stream)
+        return out

@@ -1,0 +1,161 @@
+"""Python binding of librf3 (include/rf3.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and takes torch
+tensors that live on the GPU (torch is used for device memory and streams; all
+arithmetic runs in librf3's HIP kernels).  There is no CPU fallback: if
+librf3.so is missing the import of this module's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librf3.so")
+
+RF_OK, RF_E_ARG, RF_E_SHAPE, RF_E_SIGMA, RF_E_HIP, RF_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+RF_FP32, RF_FP64 = 0, 1
+RF_Q_LITERAL, RF_Q_VARMATCH, RF_Q_FIT = 0, 1, 2
+QMODES = {"literal": RF_Q_LITERAL, "varmatch": RF_Q_VARMATCH, "fit": RF_Q_FIT}
+
+
+class rf_grid(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("nx", "ny", "nlev", "mask_nlev", "sigma_nlev", "n_img", "qmode", "k1")]
+
+    def __repr__(self):
+        return "rf_grid(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_) + ")"
+
+
+class rf_batch_item(ctypes.Structure):
+    _fields_ = [("g", ctypes.POINTER(rf_grid)), ("coef", ctypes.c_void_p), ("in_", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("nfields", ctypes.c_int32)]
+
+
+class RFError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {rf_strerror(status)} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librf3.so (built in-tree by paper_1404_5756_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1404_5756_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, S = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        G = ctypes.POINTER(rf_grid)
+        B = ctypes.POINTER(rf_batch_item)
+        L.rf_coeffs_bytes.restype = S
+        L.rf_coeffs_bytes.argtypes = [G]
+        L.rf_coeffs.restype = I
+        L.rf_coeffs.argtypes = [G, P, P, P, P, P]
+        for name in ("rf3_apply_xy", "rf3_adjoint_xy"):
+            f = getattr(L, name)
+            f.restype = I
+            f.argtypes = [G, P, I, P, P, I, I, P]
+        L.rf1_apply_xy.restype = I
+        L.rf1_apply_xy.argtypes = [G, P, I, I, P, P, I, I, P]
+        L.rf3_batch_plan_bytes.restype = S
+        L.rf3_batch_plan_bytes.argtypes = [B, I]
+        L.rf3_batch_plan.restype = I
+        L.rf3_batch_plan.argtypes = [B, I, P, S]
+        L.rf3_apply_batch.restype = I
+        L.rf3_apply_batch.argtypes = [B, I, I, I, P, S, P]
+        L.rf_strerror.restype = ctypes.c_char_p
+        L.rf_strerror.argtypes = [I]
+        _lib = L
+    return _lib
+
+
+def rf_strerror(status: int) -> str:
+    return lib().rf_strerror(int(status)).decode()
+
+
+def _check(status, where):
+    if status != RF_OK:
+        raise RFError(status, where)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def make_grid(nx, ny, nlev, mask_nlev=1, sigma_nlev=1, n_img=0, qmode=RF_Q_LITERAL, k1=5) -> rf_grid:
+    if isinstance(qmode, str):
+        qmode = QMODES[qmode]
+    return rf_grid(nx, ny, nlev, mask_nlev, sigma_nlev, n_img, qmode, k1)
+
+
+def rf_coeffs_bytes(g: rf_grid) -> int:
+    return lib().rf_coeffs_bytes(ctypes.byref(g))
+
+
+def rf_coeffs(g, mask, sigma_x, sigma_y, coef, stream=None):
+    _check(lib().rf_coeffs(ctypes.byref(g), _ptr(mask), _ptr(sigma_x), _ptr(sigma_y), _ptr(coef),
+                           _stream(stream)), "rf_coeffs")
+
+
+def rf3_apply_xy(g, coef, prec, inp, out, nlev, nfields, stream=None):
+    _check(lib().rf3_apply_xy(ctypes.byref(g), _ptr(coef), int(prec), _ptr(inp), _ptr(out), int(nlev),
+                              int(nfields), _stream(stream)), "rf3_apply_xy")
+
+
+def rf3_adjoint_xy(g, coef, prec, inp, out, nlev, nfields, stream=None):
+    _check(lib().rf3_adjoint_xy(ctypes.byref(g), _ptr(coef), int(prec), _ptr(inp), _ptr(out), int(nlev),
+                                int(nfields), _stream(stream)), "rf3_adjoint_xy")
+
+
+def rf1_apply_xy(g, coef, prec, K, inp, out, nlev, nfields, stream=None):
+    _check(lib().rf1_apply_xy(ctypes.byref(g), _ptr(coef), int(prec), int(K), _ptr(inp), _ptr(out),
+                              int(nlev), int(nfields), _stream(stream)), "rf1_apply_xy")
+
+
+def _items(items):
+    arr = (rf_batch_item * len(items))()
+    keep = []
+    for k, (g, coef, inp, out, nf) in enumerate(items):
+        keep.append(g)
+        arr[k] = rf_batch_item(ctypes.pointer(g), _ptr(coef), _ptr(inp), _ptr(out), int(nf))
+    return arr, keep
+
+
+def rf3_batch_plan_bytes(items) -> int:
+    arr, _keep = _items(items)
+    return lib().rf3_batch_plan_bytes(arr, len(items))
+
+
+def rf3_batch_plan(items) -> bytes:
+    """Host work list for `items` [(grid, coef, in, out, nfields), ...]; copy it to the device yourself."""
+    arr, _keep = _items(items)
+    nb = lib().rf3_batch_plan_bytes(arr, len(items))
+    if nb == 0:
+        raise RFError(RF_E_ARG, "rf3_batch_plan_bytes")
+    buf = ctypes.create_string_buffer(nb)
+    _check(lib().rf3_batch_plan(arr, len(items), buf, nb), "rf3_batch_plan")
+    return buf.raw
+
+
+def rf3_apply_batch(items, prec, adjoint, plan_dev, plan_bytes, stream=None):
+    arr, _keep = _items(items)
+    _check(lib().rf3_apply_batch(arr, len(items), int(prec), int(adjoint), _ptr(plan_dev), int(plan_bytes),
+                                 _stream(stream)), "rf3_apply_batch")

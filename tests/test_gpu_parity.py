@@ -1,0 +1,188 @@
+"""GPU parity: librf3 (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances (relative L2 over the whole output, which is zero off sea):
+  FP64 path: 1e-12; FP32 path: 1e-5 (stated in the performance target).
+Coefficient tables: FP64 to 1e-14 relative; coast codes bit-exact.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1404_5756_amd import rf3, synth
+from paper_1404_5756_amd.operator import HorizontalCovariance
+
+pytestmark = pytest.mark.gpu
+
+TOL32, TOL64 = 1e-5, 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def problem_of(orc, w):
+    return orc.Problem(w.mask, w.sigma_x, w.sigma_y, n_img=w.n_img, qmode=orc.QMODES[w.qmode], k1=5)
+
+
+def op_of(w):
+    return HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode, k1=5)
+
+
+CASES = [
+    # seed, ny, nx, nlev, land, n_img, qmode, mask_3d, sigma_3d, sigma range
+    (1, 37, 53, 2, 0.3, 0, "literal", False, False, (1.0, 8.0)),
+    (2, 64, 64, 1, 0.0, 0, "fit", False, False, (4.0, 4.0)),
+    (3, 131, 97, 3, 0.35, 2, "fit", False, False, (1.5, 12.0)),
+    (4, 45, 300, 2, 0.25, 4, "varmatch", True, False, (2.0, 10.0)),
+    (5, 200, 33, 2, 0.4, 1, "literal", False, True, (1.0, 6.0)),
+    (6, 1, 70, 1, 0.2, 3, "fit", False, False, (2.0, 5.0)),
+    (7, 90, 1, 1, 0.2, 3, "fit", False, False, (2.0, 5.0)),
+    (8, 260, 517, 2, 0.3, 4, "fit", True, True, (1.5, 12.0)),
+    (9, 129, 1100, 1, 0.3, 4, "fit", False, False, (2.0, 12.0)),
+]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=lambda c: f"s{c[0]}_{c[2]}x{c[1]}x{c[3]}_{c[6]}")
+def case(request, orc):
+    seed, ny, nx, nlev, land, n_img, qmode, m3, s3, sig = request.param
+    w = synth.random_case(seed, ny, nx, nlev, land, n_img, sig, 3.0, qmode, m3, s3)
+    w.nfields = 2
+    x = w.field(np.float64)
+    P = problem_of(orc, w)
+    return w, x, P, P.rf3(x), P.rf3_adjoint(x), op_of(w)
+
+
+def test_fp64_forward(case):
+    w, x, P, ref, _, op = case
+    print(f"case {w.name} fp64 forward", flush=True)
+    out = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert rel(out, ref) <= TOL64
+
+
+def test_fp64_adjoint(case):
+    w, x, P, _, refa, op = case
+    out = op.adjoint(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert rel(out, refa) <= TOL64
+
+
+def test_fp32_forward(case):
+    w, x, P, _, _, op = case
+    x32 = x.astype(np.float32)
+    ref = P.rf3(x32.astype(np.float64))
+    out = op.apply(torch.from_numpy(x32).cuda()).cpu().numpy()
+    e = rel(out, ref)
+    print(f"case {w.name} fp32 forward rel err {e:.2e}", flush=True)
+    assert e <= TOL32
+
+
+def test_fp32_adjoint(case):
+    w, x, P, _, _, op = case
+    x32 = x.astype(np.float32)
+    ref = P.rf3_adjoint(x32.astype(np.float64))
+    out = op.adjoint(torch.from_numpy(x32).cuda()).cpu().numpy()
+    e = rel(out, ref)
+    print(f"case {w.name} fp32 adjoint rel err {e:.2e}", flush=True)
+    assert e <= TOL32
+
+
+def test_fp32_in_place(case):
+    w, x, P, _, _, op = case
+    x32 = torch.from_numpy(x.astype(np.float32)).cuda()
+    ref = op.apply(x32).cpu().numpy()
+    y = x32.clone()
+    op.apply(y, out=y)
+    assert np.array_equal(y.cpu().numpy(), ref)
+
+
+def test_rf1_fp64(case):
+    w, x, P, _, _, op = case
+    ref = P.rf1(x, K=5)
+    out = op.rf1(torch.from_numpy(x).cuda(), K=5).cpu().numpy()
+    assert rel(out, ref) <= TOL64
+
+
+def test_deterministic_reruns(case):
+    w, x, P, _, _, op = case
+    x32 = torch.from_numpy(x.astype(np.float32)).cuda()
+    a = op.apply(x32)
+    b = op.apply(x32)
+    assert torch.equal(a, b)
+
+
+def _block(op):
+    return op.coef.cpu().numpy()
+
+
+def test_coefficient_tables_match_oracle(case, orc):
+    w, x, P, _, _, op = case
+    blk = _block(op)
+    hdr = np.frombuffer(blk[:256].tobytes(), dtype=np.uint64)
+    # header: magic/version (8 B), grid (32 B), npts_c, npts_m, then 6 offset pairs
+    off = {name: hdr[7 + 2 * k: 9 + 2 * k] for k, name in enumerate(("f32", "a32", "d32", "f64", "r1", "code"))}
+    npts = w.nx * w.ny * w.sigma_x.shape[0]
+    for d, sig in enumerate((w.sigma_x, w.sigma_y)):
+        f64 = np.frombuffer(blk[off["f64"][d]: off["f64"][d] + 32 * npts].tobytes(), np.float64).reshape(-1, 4)
+        ref = orc.coef3(sig.ravel(), orc.QMODES[w.qmode])
+        np.testing.assert_allclose(f64[:, 1:].T, ref[:3], rtol=1e-14, atol=1e-15)
+        # beta = (2 pi sigma^2)^(1/4) (1 - sum alpha): the printed difference loses ~log10(1/gamma) digits
+        np.testing.assert_allclose(f64[:, 0], ref[3], rtol=1e-12)
+        r1 = np.frombuffer(blk[off["r1"][d]: off["r1"][d] + 16 * npts].tobytes(), np.float64).reshape(-1, 2)
+        ref1 = orc.coef1(sig.ravel(), 5)
+        np.testing.assert_allclose(r1.T, ref1, rtol=1e-13, atol=1e-15)
+
+
+def test_coast_codes_match_oracle_segments(case, orc):
+    w, x, P, _, _, op = case
+    blk = _block(op)
+    hdr = np.frombuffer(blk[:256].tobytes(), dtype=np.uint64)
+    code_off = hdr[17:19]
+    ml = w.mask.shape[0]
+    for d in range(2):
+        codes = blk[code_off[d]: code_off[d] + ml * w.nx * w.ny].reshape(ml, w.ny, w.nx)
+        for l in range(ml):
+            lines = w.mask[l] if d == 0 else w.mask[l].T
+            cl = codes[l] if d == 0 else codes[l].T
+            for k in range(lines.shape[0]):
+                seg, kind, segs = orc.segments(lines[k], w.n_img)
+                exp = (kind == 1).astype(np.uint8) | ((kind != 0).astype(np.uint8) << 3)
+                fres = (kind == 0).astype(np.uint8)
+                bres = (kind == 0).astype(np.uint8)
+                for a, e in segs:
+                    fres[a] = 1
+                    bres[e] = 1
+                exp |= fres << 1 | bres << 2
+                assert np.array_equal(cl[k], exp), (d, l, k)
+
+
+def test_invalid_sigma_is_reported():
+    n = 16
+    mask = np.ones((1, n, n), np.uint8)
+    mask[0, :, 8:] = 0
+    s = np.full((1, n, n), 3.0)
+    s[0, :, 12:] = -1.0      # land beyond the imaginary band: never read
+    HorizontalCovariance(mask, s, s, 1, n_img=2)
+    s[0, 5, 9] = np.nan      # imaginary point (n_img=2): must be valid
+    with pytest.raises(rf3.RFError) as e:
+        HorizontalCovariance(mask, s, s, 1, n_img=2)
+    assert e.value.status == rf3.RF_E_SIGMA
+
+
+def test_c1_impulse_and_noise(orc):
+    w = synth.c1_impulse_box()
+    P = problem_of(orc, w)
+    op = op_of(w)
+    for x in (w.extra["impulse"], w.field(np.float64)):
+        ref = P.rf3(x)
+        out = op.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+        assert rel(out, ref) <= TOL64
+        ref1 = P.rf1(x, K=5)
+        out1 = op.rf1(torch.from_numpy(x).cuda(), K=5).cpu().numpy()
+        assert rel(out1, ref1) <= TOL64
+    # impulse response of the 2-D filter peaks at the impulse with ~2 pi sigma^2 mass
+    h = op.apply(torch.from_numpy(w.extra["impulse"]).cuda()).cpu().numpy()[0, 0]
+    assert np.unravel_index(np.argmax(h), h.shape) == (32, 32)

@@ -1,0 +1,193 @@
+"""Throughput of the 3rd-RF horizontal covariance operator V_H and its adjoint on one MI355X.
+
+Step = one forward application V_H x (G_y G_x) plus one adjoint application
+V_H^T x (G_x^T G_y^T) of the FP32 3rd-RF on the global quarter-degree-shaped
+workload: 1440 x 720 grid, 50 levels, ~30% land, sigma = 1.5 + 10.5 cos^2(lat)
+grid points, 4 imaginary points per coast, fitted q(sigma).  Inputs are
+resident in device memory before the timed region; the coefficient block is
+built once (setup, outside the timed region, as in the paper's scheme where
+coefficients depend only on the grid).
+
+Prints ONE JSON line.  Extra keys: per-direction kernel times, the FP64 1st-RF
+(K = 5) baseline on the same grid and the speedup of the FP32 3rd-RF forward
+over it, and the FP64 CPU oracle timed on a sample of levels.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpoints/s of 3rd-RF fwd+adjoint (FP32 batched vs FP64 1st-RF) and % HBM peak"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1404_5756_amd", "csrc", "sweep_fast.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
+    ap.add_argument("--cpu-levels", type=int, default=0,
+                    help="levels of the workload the CPU oracle runs on (0 = all levels)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-rf1", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); every (field, level) is an "
+              "independent V_H application, so N GPUs would shard levels with no communication.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1404_5756_amd import synth
+    from paper_1404_5756_amd.operator import HorizontalCovariance
+
+    dev = torch.device("cuda:0")
+    w = synth.c3_global() if args.workload == "c3" else synth.c2_regional()
+    log(f"workload {w.name}: {w.nx}x{w.ny}x{w.nlev} x {w.nfields} fields, {w.points / 1e6:.2f} M points")
+    t0 = time.time()
+    op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode, k1=5,
+                              device=dev)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    x_host = w.field(np.float32)
+    x = torch.from_numpy(x_host).to(dev)
+    out_f = torch.empty_like(x)
+    out_a = torch.empty_like(x)
+    pts = w.points
+    stream = torch.cuda.current_stream()
+
+    # ---- the step: forward + adjoint
+    for _ in range(args.warmup):
+        op.apply(x, out=out_f)
+        op.adjoint(x, out=out_a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        op.apply(x, out=out_f)
+        op.adjoint(x, out=out_a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = pts / (ms_step * 1e-3) / 1e9
+    log(f"step (fwd+adj): {ms_step:.3f} ms -> {value:.1f} Gpoints/s")
+
+    # ---- per-kernel times (each call of rf3_apply_dir is one kernel launch)
+    reps = max(5, args.steps)
+    kern = {}
+    for name, d, adj in (("x_fwd", 0, False), ("y_fwd", 1, False), ("y_adj", 1, True), ("x_adj", 0, True)):
+        dst = out_f if not adj else out_a
+        op.apply_dir(x, d, adj, out=dst)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            op.apply_dir(x, d, adj, out=dst)
+        b.record(stream)
+        torch.cuda.synchronize()
+        kern[name] = a.elapsed_time(b) / reps
+    log("kernel ms: " + ", ".join(f"{k} {v:.3f}" for k, v in kern.items()))
+    dom = max(kern, key=kern.get)
+    bytes_per_launch = 8.0 * pts        # FP32 read + write of every point once
+    achieved = bytes_per_launch / (kern[dom] * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if tf.get("kernel_src_sha256") == src_hash and dom in tf.get("bytes_per_launch", {}):
+            traffic = tf["bytes_per_launch"][dom]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+    step_frac = 4 * bytes_per_launch / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    # ---- forward alone and the FP64 1st-RF baseline (K = 5), same grid and field
+    e0.record(stream)
+    for _ in range(reps):
+        op.apply(x, out=out_f)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1) / reps
+    rf1 = None
+    if not args.no_rf1:
+        x64 = x.double()
+        o64 = torch.empty_like(x64)
+        op.rf1(x64, K=5, out=o64)
+        torch.cuda.synchronize()
+        r1reps = 3
+        e0.record(stream)
+        for _ in range(r1reps):
+            op.rf1(x64, K=5, out=o64)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_rf1 = e0.elapsed_time(e1) / r1reps
+        rf1 = {"ms": round(ms_rf1, 3), "gpoints_s": round(pts / (ms_rf1 * 1e-3) / 1e9, 2),
+               "speedup_rf3_fp32_fwd_vs_rf1_fp64_k5": round(ms_rf1 / ms_fwd, 2)}
+        log(f"1st-RF FP64 K=5: {ms_rf1:.3f} ms; 3rd-RF FP32 forward {ms_fwd:.3f} ms")
+        del x64, o64
+
+    # ---- CPU oracle baseline on a sample of levels, and parity on that sample
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        import oracle
+        oracle.build()
+        nl = w.nlev if args.cpu_levels <= 0 else max(1, min(args.cpu_levels, w.nlev))
+        P = oracle.Problem(w.mask, w.sigma_x, w.sigma_y, n_img=w.n_img, qmode=oracle.QMODES[w.qmode], k1=5)
+        xs = x_host[:1, :nl].astype(np.float64)
+        threads = os.cpu_count() or 1
+        t0 = time.time()
+        ref_f = P.rf3(xs, threads=threads)
+        ref_a = P.rf3_adjoint(xs, threads=threads)
+        cpu_s = time.time() - t0
+        sample_pts = w.nx * w.ny * nl
+        cpu = {"value": round(sample_pts / (cpu_s / 1.0) / 1e9, 5), "unit": "Gpoints/s", "cores": threads,
+               "kind": "oracle", "seconds": round(cpu_s, 2),
+               "sample": f"fwd+adj V_H of {nl} of {w.nlev} levels ({sample_pts / 1e6:.2f} M points), FP64 C oracle, "
+                         f"OpenMP over lines"}
+        op.apply(x, out=out_f)
+        op.adjoint(x, out=out_a)
+        torch.cuda.synchronize()
+        gf = out_f[:1, :nl].double().cpu().numpy()
+        ga = out_a[:1, :nl].double().cpu().numpy()
+        parity = {"levels": nl,
+                  "fwd_rel_l2": float(np.linalg.norm(gf - ref_f) / np.linalg.norm(ref_f)),
+                  "adj_rel_l2": float(np.linalg.norm(ga - ref_a) / np.linalg.norm(ref_a)), "tol": 1e-5}
+        log(f"cpu oracle: {cpu_s:.2f} s on {threads} threads; parity {parity}")
+
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Gpoints/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{w.name}: fwd+adjoint V_H, FP32, {w.nx}x{w.ny} grid x {w.nlev} levels x "
+                               f"{w.nfields} field, n_img={w.n_img}, q={w.qmode}", "points": pts,
+                   "step": "rf3_apply_xy + rf3_adjoint_xy", "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "hbm_frac_step": round(step_frac, 4),
+        "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
+        "rf3_fwd_ms": round(ms_fwd, 4),
+        "rf1_fp64_k5": rf1,
+        "parity_sample": parity,
+        "setup_s": round(setup_s, 2),
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

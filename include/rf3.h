@@ -112,6 +112,14 @@ int rf3_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, const void *i
 int rf3_adjoint_xy(const rf_grid *g, const void *coef, rf_prec prec, const void *in,
                    void *out, int32_t nlev, int32_t nfields, void *stream);
 
+/* One direction of the 3rd-RF: out = G_x in (dir = 0, every row) or
+ * out = G_y in (dir = 1, every column); adjoint = 1 applies the transpose of
+ * that direction instead.  rf3_apply_xy is rf3_apply_dir(x) followed by
+ * rf3_apply_dir(y) in place on out; rf3_adjoint_xy runs y^T then x^T.  Same
+ * conventions as rf3_apply_xy. */
+int rf3_apply_dir(const rf_grid *g, const void *coef, rf_prec prec, int32_t dir, int32_t adjoint,
+                  const void *in, void *out, int32_t nlev, int32_t nfields, void *stream);
+
 /* out = G_y^(K) G_x^(K) in with the 1st-RF: K causal+anti-causal iterations
  * along x (eqs. "proc1-1", "proc1-2"), then K along y.  K must equal g->k1
  * (the coefficients depend on K).  Only RF_FP64 is provided: this is the

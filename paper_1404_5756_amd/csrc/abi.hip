@@ -1,6 +1,7 @@
 // C-ABI entry points of librf3: argument checks, then kernel launches on the
 // caller's stream.  No call allocates memory or synchronises, except
 // rf_coeffs (coef.hip), which reports invalid sigma.
+#include <stdlib.h>
 #include <string.h>
 
 #include "rf3_internal.h"
@@ -50,20 +51,48 @@ const T *tab(const void *coef, uint64_t off)
     return reinterpret_cast<const T *>(reinterpret_cast<const char *>(coef) + off);
 }
 
+// RF3_SEQUENTIAL=1 in the environment selects the line-sequential FP32 kernels
+// (a cross-check of the tiled kernels); read at every call.
+bool force_sequential()
+{
+    const char *e = getenv("RF3_SEQUENTIAL");
+    return e && e[0] == '1';
+}
+
 }  // namespace
 
-// One direction of the 3rd-RF in FP32 (forward when adj is false).
+// One direction of the 3rd-RF in FP32 (forward when adj is false).  The tiled
+// kernels need one 2-D mask and 2-D sigma for all levels; other cases run the
+// line-sequential kernels.
 static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void *coef, int dir,
                               bool adj, const float *in, float *out, int nlev, int nfields,
                               hipStream_t st)
 {
+    const bool tiled2d = g->mask_nlev == 1 && g->sigma_nlev == 1 && !force_sequential();
+    const int nplanes = nlev * nfields;
+    if (tiled2d && dir == 0 && h.lx) {
+        hipError_t e = fast_rf3_x(in, out, tab<float4>(coef, h.off_f32[0]), tab<uint64_t>(coef, h.off_lmx), h.lx,
+                                  g->nx, g->ny, nplanes, adj, st);
+        if (e != hipErrorNotSupported) return e;
+    }
+    if (tiled2d && dir == 1 && h.ly) {
+        hipError_t e = fast_rf3_y(in, out, tab<float4>(coef, h.off_f32[1]), tab<uint64_t>(coef, h.off_lmy),
+                                  tab<float>(coef, h.off_phiy), h.ly, g->nx, g->ny, nplanes, adj, st);
+        if (e != hipErrorNotSupported) return e;
+    }
     const LineGeom G = geom(g, dir, nlev, nfields);
     const float4 *T1 = tab<float4>(coef, adj ? h.off_a32[dir] : h.off_f32[dir]);
     const float4 *T2 = tab<float4>(coef, adj ? h.off_d32[dir] : h.off_f32[dir]);
-    const uint8_t *code = tab<uint8_t>(coef, h.off_code[dir]);
-    hipError_t e = fast_rf3_f32(in, out, T1, T2, code, G, dir, adj, st);
-    if (e == hipErrorNotSupported) e = seq_rf3_f32(in, out, T1, T2, code, G, adj, st);
-    return e;
+    return seq_rf3_f32(in, out, T1, T2, tab<uint8_t>(coef, h.off_code[dir]), G, adj, st);
+}
+
+static hipError_t rf3_dir(const rf_grid *g, const BlockHeader &h, const void *coef, rf_prec prec, int dir,
+                          bool adj, const void *in, void *out, int nlev, int nfields, hipStream_t st)
+{
+    if (prec == RF_FP32)
+        return rf3_dir_f32(g, h, coef, dir, adj, (const float *)in, (float *)out, nlev, nfields, st);
+    return seq_rf3_f64((const double *)in, (double *)out, tab<double4>(coef, h.off_f64[dir]),
+                       tab<uint8_t>(coef, h.off_code[dir]), geom(g, dir, nlev, nfields), adj, st);
 }
 
 static int rf3_run(const rf_grid *g, const void *coef, rf_prec prec, const void *in, void *out,
@@ -75,18 +104,20 @@ static int rf3_run(const rf_grid *g, const void *coef, rf_prec prec, const void 
     const BlockHeader h = layout(g);
     // forward: x then y;  adjoint: y then x.  The second pass runs in place on out.
     const int d0 = adj ? 1 : 0, d1 = adj ? 0 : 1;
-    hipError_t e;
-    if (prec == RF_FP32) {
-        e = rf3_dir_f32(g, h, coef, d0, adj, (const float *)in, (float *)out, nlev, nfields, st);
-        if (e == hipSuccess)
-            e = rf3_dir_f32(g, h, coef, d1, adj, (const float *)out, (float *)out, nlev, nfields, st);
-    } else {
-        e = seq_rf3_f64((const double *)in, (double *)out, tab<double4>(coef, h.off_f64[d0]),
-                        tab<uint8_t>(coef, h.off_code[d0]), geom(g, d0, nlev, nfields), adj, st);
-        if (e == hipSuccess)
-            e = seq_rf3_f64((const double *)out, (double *)out, tab<double4>(coef, h.off_f64[d1]),
-                            tab<uint8_t>(coef, h.off_code[d1]), geom(g, d1, nlev, nfields), adj, st);
-    }
+    hipError_t e = rf3_dir(g, h, coef, prec, d0, adj, in, out, nlev, nfields, st);
+    if (e == hipSuccess) e = rf3_dir(g, h, coef, prec, d1, adj, out, out, nlev, nfields, st);
+    return e == hipSuccess ? RF_OK : RF_E_HIP;
+}
+
+extern "C" int rf3_apply_dir(const rf_grid *g, const void *coef, rf_prec prec, int32_t dir, int32_t adjoint,
+                             const void *in, void *out, int32_t nlev, int32_t nfields, void *stream)
+{
+    const int rc = check_apply(g, coef, prec, in, out, nlev, nfields);
+    if (rc) return rc;
+    if (dir != 0 && dir != 1) return RF_E_ARG;
+    const BlockHeader h = layout(g);
+    const hipError_t e = rf3_dir(g, h, coef, prec, dir, adjoint != 0, in, out, nlev, nfields,
+                                 reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? RF_OK : RF_E_HIP;
 }
 

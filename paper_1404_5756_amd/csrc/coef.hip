@@ -18,6 +18,7 @@
 #include <math.h>
 
 #include "rf3_internal.h"
+#include "sweeps.h"
 
 namespace rf {
 
@@ -183,6 +184,62 @@ __global__ void k_coef(const double *__restrict__ sx, const double *__restrict__
     }
 }
 
+// Lane masks of the x kernel: one thread per (mask level, row, step i); bit c
+// describes point c*lx + i (points past the row end are outside every segment).
+__global__ void k_lanemask_x(const uint8_t *__restrict__ code, uint64_t *__restrict__ lm, int nx, int ny,
+                             int nl, int lx)
+{
+    const int lxp = lmx_stride(lx);
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nl * ny * lxp) return;
+    const int i = (int)(t % lxp);
+    const long lrow = t / lxp;               // level * ny + row
+    const uint8_t *c = code + lrow * nx;
+    uint64_t f = ~0ull, b = ~0ull, s = 0;   // s collects SEA; the table stores its complement
+    if (i < lx) {
+        f = b = 0;
+        for (int ch = 0; ch < 64; ++ch) {
+            const int x = ch * lx + i;
+            const uint8_t v = x < nx ? c[x] : (uint8_t)(CODE_FRESET | CODE_BRESET);
+            f |= (uint64_t)((v & CODE_FRESET) != 0) << ch;
+            b |= (uint64_t)((v & CODE_BRESET) != 0) << ch;
+            s |= (uint64_t)((v & CODE_SEA) != 0) << ch;
+        }
+    }
+    uint64_t *o = lm + lrow * 3 * lxp + i;
+    o[0] = f;
+    o[lxp] = b;
+    o[2 * lxp] = ~s;
+}
+
+// Lane masks of the y kernel: one thread per (mask level, column block, entry e
+// < lys); entry e describes row e-1 and bit j column 32*blk + j; rows and
+// columns outside the grid (and the guard entries) are outside every segment.
+__global__ void k_lanemask_y(const uint8_t *__restrict__ code, uint64_t *__restrict__ lm, int nx, int ny,
+                             int nl, int ly)
+{
+    const int nblk = (nx + kYCols - 1) / kYCols, lys = lmy_stride(ly);
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nl * nblk * lys) return;
+    const int e = (int)(t % lys), r = e - 1;
+    const long lb = t / lys;                  // level * nblk + blk
+    const int blk = (int)(lb % nblk), lev = (int)(lb / nblk);
+    uint32_t f = 0, b = 0, s = 0;
+    for (int j = 0; j < kYCols; ++j) {
+        const int x = blk * kYCols + j;
+        const uint8_t v = (x < nx && r >= 0 && r < ny) ? code[((long)lev * ny + r) * nx + x]
+                                                       : (uint8_t)(CODE_FRESET | CODE_BRESET);
+        f |= (uint32_t)((v & CODE_FRESET) != 0) << j;
+        b |= (uint32_t)((v & CODE_BRESET) != 0) << j;
+        s |= (uint32_t)((v & CODE_SEA) != 0) << j;
+    }
+    // both halves of the wave (two planes) share the column pattern
+    uint64_t *o = lm + lb * 3 * lys + e;
+    o[0] = f | ((uint64_t)f << 32);
+    o[lys] = b | ((uint64_t)b << 32);
+    o[2 * lys] = ~(s | ((uint64_t)s << 32));
+}
+
 bool grid_ok(const rf_grid *g)
 {
     if (!g) return false;
@@ -213,6 +270,15 @@ BlockHeader layout(const rf_grid *g)
         h.off_r1[d] = off;  off = align256(off + 16 * h.npts_c);
     }
     for (int d = 0; d < 2; ++d) { h.off_code[d] = off; off = align256(off + h.npts_m); }
+    h.lx = tile_lx(g->nx);
+    h.ly = tile_ly(g->ny);
+    h.off_lmx = off;
+    if (h.lx) off = align256(off + (size_t)g->mask_nlev * g->ny * lmx_stride(h.lx) * 3 * 8);
+    h.off_lmy = off;
+    if (h.ly) off = align256(off + (size_t)g->mask_nlev * ((g->nx + kYCols - 1) / kYCols) * lmy_stride(h.ly) * 3 * 8);
+    h.off_phiy = off;
+    if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1)
+        off = align256(off + (size_t)((g->nx + kYCols - 1) / kYCols) * 4 * kYWaves * kYCols * 12 * 4);
     h.total_bytes = off;
     return h;
 }
@@ -245,6 +311,25 @@ extern "C" int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *si
     k_coef<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(sigma_x, sigma_y, (const uint8_t *)(blk + h.off_code[0]),
                                                        (const uint8_t *)(blk + h.off_code[1]), blk, h);
     if (hipGetLastError() != hipSuccess) return RF_E_HIP;
+    if (h.lx) {
+        const long n = (long)g->mask_nlev * g->ny * lmx_stride(h.lx);
+        k_lanemask_x<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((const uint8_t *)(blk + h.off_code[0]),
+                                                                (uint64_t *)(blk + h.off_lmx), g->nx, g->ny,
+                                                                g->mask_nlev, h.lx);
+        if (hipGetLastError() != hipSuccess) return RF_E_HIP;
+    }
+    if (h.ly) {
+        const long n = (long)g->mask_nlev * ((g->nx + kYCols - 1) / kYCols) * lmy_stride(h.ly);
+        k_lanemask_y<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((const uint8_t *)(blk + h.off_code[1]),
+                                                                (uint64_t *)(blk + h.off_lmy), g->nx, g->ny,
+                                                                g->mask_nlev, h.ly);
+        if (hipGetLastError() != hipSuccess) return RF_E_HIP;
+    }
+    if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1) {
+        if (setup_phi_y((const float4 *)(blk + h.off_f32[1]), (const uint8_t *)(blk + h.off_code[1]),
+                        (float *)(blk + h.off_phiy), g->nx, g->ny, h.ly, st) != hipSuccess)
+            return RF_E_HIP;
+    }
     int32_t err = 0;
     if (hipMemcpyAsync(&err, blk + offsetof(BlockHeader, sigma_error), sizeof(err), hipMemcpyDeviceToHost, st) != hipSuccess)
         return RF_E_HIP;

@@ -78,6 +78,15 @@ class HorizontalCovariance:
         rf3.rf3_adjoint_xy(self.grid, self.coef, self._prec(x), x, out, nl, nf, stream)
         return out
 
+    def apply_dir(self, x, direction, adjoint=False, out=None, stream=None):
+        """One direction only: G_x (direction 0 / 'x') or G_y (1 / 'y'), or its transpose."""
+        d = {"x": 0, "y": 1}.get(direction, direction)
+        x = x.contiguous()
+        out = torch.empty_like(x) if out is None else out
+        nf, nl = self._shape(x)
+        rf3.rf3_apply_dir(self.grid, self.coef, self._prec(x), d, int(bool(adjoint)), x, out, nl, nf, stream)
+        return out
+
     def rf1(self, x, K=None, out=None, stream=None):
         """1st-RF baseline, K iterations per direction (FP64)."""
         x = x.contiguous()

@@ -61,6 +61,8 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.restype = I
             f.argtypes = [G, P, I, P, P, I, I, P]
+        L.rf3_apply_dir.restype = I
+        L.rf3_apply_dir.argtypes = [G, P, I, I, I, P, P, I, I, P]
         L.rf1_apply_xy.restype = I
         L.rf1_apply_xy.argtypes = [G, P, I, I, P, P, I, I, P]
         L.rf3_batch_plan_bytes.restype = S
@@ -123,6 +125,11 @@ def rf3_apply_xy(g, coef, prec, inp, out, nlev, nfields, stream=None):
 def rf3_adjoint_xy(g, coef, prec, inp, out, nlev, nfields, stream=None):
     _check(lib().rf3_adjoint_xy(ctypes.byref(g), _ptr(coef), int(prec), _ptr(inp), _ptr(out), int(nlev),
                                 int(nfields), _stream(stream)), "rf3_adjoint_xy")
+
+
+def rf3_apply_dir(g, coef, prec, direction, adjoint, inp, out, nlev, nfields, stream=None):
+    _check(lib().rf3_apply_dir(ctypes.byref(g), _ptr(coef), int(prec), int(direction), int(adjoint), _ptr(inp),
+                               _ptr(out), int(nlev), int(nfields), _stream(stream)), "rf3_apply_dir")
 
 
 def rf1_apply_xy(g, coef, prec, K, inp, out, nlev, nfields, stream=None):

@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for n in ("rf_coeffs_bytes", "rf_coeffs", "rf3_apply_xy", "rf3_adjoint_xy", "rf1_apply_xy",
+    for n in ("rf_coeffs_bytes", "rf_coeffs", "rf3_apply_xy", "rf3_adjoint_xy", "rf3_apply_dir", "rf1_apply_xy",
               "rf3_batch_plan_bytes", "rf3_batch_plan", "rf3_apply_batch", "rf_strerror"):
         assert n in names
 
@@ -59,7 +59,7 @@ def test_coeffs_bytes_validates_grid(rf3):
     assert L.rf_coeffs_bytes(None) == 0
     # 3-D sigma and mask make the tables per level
     g3 = rf3.make_grid(100, 50, 10, mask_nlev=10, sigma_nlev=10)
-    assert L.rf_coeffs_bytes(ctypes.byref(g3)) > 9 * n
+    assert L.rf_coeffs_bytes(ctypes.byref(g3)) > 10 * 100 * 50 * (16 * 3 + 32 + 16) * 2
 
 
 FAKE = 0x7f0000000000  # never dereferenced: every call below fails its host-side checks
@@ -86,6 +86,15 @@ def test_apply_argument_errors(rf3):
         assert fn(gp, FAKE, 1, FAKE, FAKE + 64 * 32 * 4 * 4, 4, 1, None) == E_ARG  # FP64 is twice as long
     bad = rf3.make_grid(64, 32, 4, qmode=7)
     assert L.rf3_apply_xy(ctypes.byref(bad), FAKE, 0, FAKE, FAKE, 4, 1, None) == E_SHAPE
+
+
+def test_apply_dir_argument_errors(rf3):
+    L = rf3.lib()
+    g = rf3.make_grid(64, 32, 4)
+    gp = ctypes.byref(g)
+    assert L.rf3_apply_dir(gp, FAKE, 0, 2, 0, FAKE, FAKE + 10 ** 7, 4, 1, None) == rf3.RF_E_ARG
+    assert L.rf3_apply_dir(gp, FAKE, 0, -1, 0, FAKE, FAKE + 10 ** 7, 4, 1, None) == rf3.RF_E_ARG
+    assert L.rf3_apply_dir(gp, FAKE, 0, 0, 0, FAKE, FAKE + 8, 4, 1, None) == rf3.RF_E_ARG
 
 
 def test_rf1_argument_errors(rf3):

@@ -71,8 +71,8 @@ static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void
     const bool tiled2d = g->mask_nlev == 1 && g->sigma_nlev == 1 && !force_sequential();
     const int nplanes = nlev * nfields;
     if (tiled2d && dir == 0 && h.lx) {
-        hipError_t e = fast_rf3_x(in, out, tab<float4>(coef, h.off_f32[0]), tab<uint64_t>(coef, h.off_lmx), h.lx,
-                                  g->nx, g->ny, nplanes, adj, st);
+        hipError_t e = fast_rf3_x(in, out, tab<float4>(coef, h.off_f32[0]), tab<uint64_t>(coef, h.off_lmx),
+                                  tab<float>(coef, h.off_phix), h.lx, g->nx, g->ny, nplanes, adj, st);
         if (e != hipErrorNotSupported) return e;
     }
     if (tiled2d && dir == 1 && h.ly) {

@@ -279,6 +279,8 @@ BlockHeader layout(const rf_grid *g)
     h.off_phiy = off;
     if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1)
         off = align256(off + (size_t)((g->nx + kYCols - 1) / kYCols) * 4 * kYWaves * kYCols * 12 * 4);
+    h.off_phix = off;
+    if (h.lx && g->mask_nlev == 1 && g->sigma_nlev == 1) off = align256(off + (size_t)g->ny * 4 * 64 * 12 * 4);
     h.total_bytes = off;
     return h;
 }
@@ -324,6 +326,11 @@ extern "C" int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *si
                                                                 (uint64_t *)(blk + h.off_lmy), g->nx, g->ny,
                                                                 g->mask_nlev, h.ly);
         if (hipGetLastError() != hipSuccess) return RF_E_HIP;
+    }
+    if (h.lx && g->mask_nlev == 1 && g->sigma_nlev == 1) {
+        if (setup_phi_x((const float4 *)(blk + h.off_f32[0]), (const uint8_t *)(blk + h.off_code[0]),
+                        (float *)(blk + h.off_phix), g->nx, g->ny, h.lx, st) != hipSuccess)
+            return RF_E_HIP;
     }
     if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1) {
         if (setup_phi_y((const float4 *)(blk + h.off_f32[1]), (const uint8_t *)(blk + h.off_code[1]),

@@ -10,7 +10,7 @@
 namespace rf {
 
 constexpr uint32_t kMagic = 0x52463321u;   // "RF3!"
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 
 // Per-point coast code bits (one byte per point and direction).
 enum : uint8_t {
@@ -50,22 +50,22 @@ struct BlockHeader {
     uint64_t off_lmx;         // uint64 [mask_nlev][ny][3][lxp]: FRESET, BRESET, not-SEA lane masks, bit c = chunk c
     uint64_t off_lmy;         // uint64 [mask_nlev][nblk][3][lys]: bits j and 32+j = column 32*blk + j, entry r+1 = row r
     uint64_t off_phiy;        // float [nblk][4][16][32][12]: y-chunk transfer matrices (2-D mask and sigma only)
+    uint64_t off_phix;        // float [ny][4][64][12]: x-chunk transfer matrices (2-D mask and sigma only)
 };
 static_assert(sizeof(BlockHeader) <= 256, "header must fit in 256 bytes");
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Tiling of the FP32 kernels.  x: one wave per row, 64 lanes each own a chunk
-// of lx consecutive points.  y: 16 waves per column block, each wave owns a
-// chunk of ly consecutive rows; lanes are 32 columns x 2 planes.
-constexpr int kLxMax = 32, kLyMax = 64, kYWaves = 16, kYCols = 32;
+// of lx consecutive points (lx odd, so that a chunk-major LDS layout is free
+// of bank conflicts).  y: 16 waves per column block, each wave owns a chunk of
+// ly consecutive rows; lanes are 32 columns x 2 planes.
+constexpr int kLxMax = 33, kLyMax = 64, kYWaves = 16, kYCols = 32;
 __host__ __device__ inline int tile_lx(int nx)
 {
     const int need = (nx + 63) / 64;
-    const int opts[] = {1, 2, 3, 4, 6, 8, 12, 16, 20, 24, 28, 32};
-    for (int o : opts)
-        if (o >= need) return o;
-    return 0;
+    if (need > kLxMax) return 0;
+    return need | 1;
 }
 // padded per-row length of the x lane-mask arrays (whole 8-entry blocks)
 __host__ __device__ inline int lmx_stride(int lx) { return (lx + 7) & ~7; }

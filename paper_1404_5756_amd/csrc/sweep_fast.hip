@@ -111,23 +111,52 @@ __device__ __forceinline__ void mat_acc(const float *A, const St &x, St &y)
     y.c = fmaf(A[6], x.a, fmaf(A[7], x.b, fmaf(A[8], x.c, y.c)));
 }
 
-__device__ __forceinline__ St st_shfl_up(const St &x, int d)
-{
-    return St{__shfl_up(x.a, d, 64), __shfl_up(x.b, d, 64), __shfl_up(x.c, d, 64)};
-}
-__device__ __forceinline__ St st_shfl_down(const St &x, int d)
-{
-    return St{__shfl_down(x.a, d, 64), __shfl_down(x.b, d, 64), __shfl_down(x.c, d, 64)};
-}
 
 }  // namespace
 
 // ======================================================================
-// x direction: one wave per line (row), lane c owns points [c*L, c*L + L).
-// All waves of a workgroup work on the same row (different planes), so the
-// row's coefficients, lane masks and scan matrices are shared.
+// x direction: one wave per line (a row of one plane); lane c owns points
+// [c*L, c*L + L) with L odd.  All waves of a workgroup work on lines of the
+// same row, which share its coefficients, lane masks and scan matrices.
+// Loads go straight into the chunk layout (range-checked buffer loads; the
+// next line is prefetched into registers while the current one is filtered).
+// Results go through LDS so that the stores are coalesced; the odd L keeps the
+// chunk-major LDS writes free of bank conflicts.
 // ======================================================================
 constexpr int kXWaves = 4;
+
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+
+// raw buffer over nbytes at p: loads past the end read 0, stores past it are dropped
+__device__ __forceinline__ Rsrc make_rsrc(const void *p, uint32_t nbytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)nbytes, 0x00020000);
+}
+
+// L consecutive floats at byte offset off into v (dwordx4 groups, then the rest)
+template <int L>
+__device__ __forceinline__ void chunk_load(Rsrc r, int off, float *v)
+{
+#pragma unroll
+    for (int j = 0; j + 4 <= L; j += 4) {
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off + 4 * j, 0, 0);
+        v[j] = __uint_as_float(a.x);
+        v[j + 1] = __uint_as_float(a.y);
+        v[j + 2] = __uint_as_float(a.z);
+        v[j + 3] = __uint_as_float(a.w);
+    }
+    constexpr int j = L & ~3, rem = L & 3;
+    if (rem == 3) {
+        const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, off + 4 * j, 0, 0);
+        v[j] = __uint_as_float(a.x);
+        v[j + 1] = __uint_as_float(a.y);
+        v[j + 2] = __uint_as_float(a.z);
+    }
+    if (rem == 1) v[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off + 4 * j, 0, 0));
+    static_assert(rem != 2, "L is odd");
+}
 
 template <int L, bool ADJ>
 struct XRow {
@@ -135,29 +164,25 @@ struct XRow {
     float kb[L], kg[L], k2[L], k3[L];          // beta, gamma, c2, c3 of my chunk's points
     const uint64_t *lm;                        // this row's masks: [3][LP] FRESET, BRESET, not-SEA
 
-    // ascending sweep over my chunk.  MODE 0: zero input (homogeneous),
-    // 1: input v, no output, 2: input v, output written back into v.
+    // ascending sweep over my chunk.  MODE 1: input v, no output;
+    // MODE 2: input v, output written back into v.
     template <int MODE>
     __device__ __forceinline__ void asc(St &x, float *v) const
     {
-        // forward: zero the state before a segment start; adjoint: after a segment end
-        const uint64_t *rp = lm + (ADJ ? LP : 0);
+        // forward: zero the state before a segment start; adjoint: after a segment end.
+        // The opaque zero keeps this pass's mask loads inside the pass.
+        const uint64_t *rp = lm + (ADJ ? LP : 0) + fresh_int(0);
 #pragma unroll
-        for (int b = 0; b < LP / 8; ++b) {
-            const u32x16 m = sload16(rp + 8 * b);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int i = 8 * b + q;
-                if (i >= L) break;
-                if (!ADJ) {
-                    st_reset(x, m64_of(m, q));
-                    fwd_step(x, MODE ? kb[i] * v[i] : 0.f, kg[i], k2[i], k3[i]);
-                    if (MODE == 2) v[i] = x.a;
-                } else {
-                    const float o = adj_step(x, MODE ? v[i] : 0.f, kb[i], kg[i], k2[i], k3[i]);
-                    st_reset(x, m64_of(m, q));
-                    if (MODE == 2) v[i] = o;
-                }
+        for (int i = 0; i < L; ++i) {
+            const uint64_t m = rp[i];
+            if (!ADJ) {
+                st_reset(x, m);
+                fwd_step(x, kb[i] * v[i], kg[i], k2[i], k3[i]);
+                if (MODE == 2) v[i] = x.a;
+            } else {
+                const float o = adj_step(x, v[i], kb[i], kg[i], k2[i], k3[i]);
+                st_reset(x, m);
+                if (MODE == 2) v[i] = o;
             }
         }
     }
@@ -166,100 +191,148 @@ struct XRow {
     __device__ __forceinline__ void desc(St &x, float *v) const
     {
         // forward: zero the state before a segment end; adjoint: after a segment start
-        const uint64_t *rp = lm + (ADJ ? 0 : LP);
+        const int z = fresh_int(0);
+        const uint64_t *rp = lm + (ADJ ? 0 : LP) + z;
+        const uint64_t *sp = lm + 2 * LP + z;
 #pragma unroll
-        for (int b = LP / 8 - 1; b >= 0; --b) {
-            const u32x16 m = sload16(rp + 8 * b);
-            u32x16 sm;
-            if (MODE == 2) sm = sload16(lm + 2 * LP + 8 * b);
-#pragma unroll
-            for (int q = 7; q >= 0; --q) {
-                const int i = 8 * b + q;
-                if (i >= L) continue;
-                if (!ADJ) {
-                    st_reset(x, m64_of(m, q));
-                    fwd_step(x, MODE ? kb[i] * v[i] : 0.f, kg[i], k2[i], k3[i]);
-                    if (MODE == 2) v[i] = zero_if(x.a, m64_of(sm, q));
-                } else {
-                    const float o = adj_step(x, MODE ? v[i] : 0.f, kb[i], kg[i], k2[i], k3[i]);
-                    st_reset(x, m64_of(m, q));
-                    if (MODE == 2) v[i] = zero_if(o, m64_of(sm, q));
-                }
+        for (int i = L - 1; i >= 0; --i) {
+            const uint64_t m = rp[i];
+            if (!ADJ) {
+                st_reset(x, m);
+                fwd_step(x, kb[i] * v[i], kg[i], k2[i], k3[i]);
+                if (MODE == 2) v[i] = zero_if(x.a, sp[i]);
+            } else {
+                const float o = adj_step(x, v[i], kb[i], kg[i], k2[i], k3[i]);
+                st_reset(x, m);
+                if (MODE == 2) v[i] = zero_if(o, sp[i]);
             }
-        }
-    }
-    // 3x3 transfer matrix of the chunk for one sweep (columns = images of the basis states)
-    template <bool DESC>
-    __device__ __forceinline__ void transfer(float *A) const
-    {
-        float dummy[L];
-        St e[3] = {{1.f, 0.f, 0.f}, {0.f, 1.f, 0.f}, {0.f, 0.f, 1.f}};
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (DESC) desc<0>(e[k], dummy);
-            else asc<0>(e[k], dummy);
-            A[0 + k] = e[k].a;
-            A[3 + k] = e[k].b;
-            A[6 + k] = e[k].c;
         }
     }
 };
 
-// Kogge-Stone over the 64 chunks of a line with precomputed matrices.
-// ks: [6 rounds][64 lanes][12] (9 used).  DESC scans from lane 63 down.
-template <bool DESC>
-__device__ __forceinline__ St ks_carry(St b, const float *ks, int lane)
+// ---- carry scan over the 64 chunks of a line, in registers (DPP) ----------
+// Chunk c maps its incoming state s to Phi_c s + b_c.  The scan turns the local
+// end states b into the state entering every chunk.  Ascending order (lane 0
+// first): four in-row rounds (row_shr 1, 2, 4, 8 within 16-lane rows), then
+// the standard row broadcasts (lane 15 -> rows 1 and 3, lane 31 -> rows 2 and
+// 3).  Descending order mirrors this with row_shl; its two cross-row rounds
+// take lane 16/48 -> rows 0/2 and lane 32 -> rows 0 and 1.  Round r adds
+// K[r] * (state received), with K[r] the product of the Phi between the two
+// chunks (zero where nothing is received).
+constexpr int kKs = 55;   // floats per lane in the round-matrix table: 6 x 9, odd stride
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xF, true));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ St st_dpp(const St &x)
+{
+    return St{dpp<CTRL, ROWMASK>(x.a), dpp<CTRL, ROWMASK>(x.b), dpp<CTRL, ROWMASK>(x.c)};
+}
+enum : int {
+    DPP_ROW_SHL = 0x100, DPP_ROW_SHR = 0x110, DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138,
+    DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143,
+};
+
+// C = A B, 3x3 row-major
+__device__ __forceinline__ void mat_mul(const float *A, const float *B, float *C)
 {
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        const int d = 1 << r;
-        const St bp = DESC ? st_shfl_down(b, d) : st_shfl_up(b, d);
-        const bool has = DESC ? lane + d < 64 : lane >= d;
-        const float4 *q = reinterpret_cast<const float4 *>(ks + (r * 64 + lane) * 12);
-        const float4 q0 = q[0], q1 = q[1], q2 = q[2];
-        const float A[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
-        St nb = b;
-        mat_acc(A, bp, nb);
-        if (has) b = nb;
-    }
-    // exclusive: state entering my chunk = inclusive state of the previous chunk
-    St c = DESC ? st_shfl_down(b, 1) : st_shfl_up(b, 1);
-    if (DESC ? lane == 63 : lane == 0) c = St{0.f, 0.f, 0.f};
-    return c;
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = fmaf(A[3 * i], B[j], fmaf(A[3 * i + 1], B[3 + j], A[3 * i + 2] * B[6 + j]));
+}
+__device__ __forceinline__ void mat_put(float *q, const float *A, bool keep)
+{
+#pragma unroll
+    for (int e = 0; e < 9; ++e) q[e] = keep ? A[e] : 0.f;
 }
 
-// round matrices A^(r) of the Kogge-Stone scan (accumulated product before round r)
+// round matrices of one scan direction from this lane's Phi; K: [64 lanes][kKs]
 template <bool DESC>
-__device__ __forceinline__ void ks_build(float *A, float *ks, int lane)
+__device__ __forceinline__ void ks_build(const float *Phi, float *K, int lane)
 {
+    const int p = lane & 15, row = lane >> 4;
+    float *k = K + lane * kKs;
+    float A[9], Q[9], T[9], N[9];
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
+    for (int e = 0; e < 9; ++e) A[e] = Q[e] = Phi[e];
+    // A: product over the d chunks ending (in scan order) at mine; Q: over my row so far
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
         const int d = 1 << r;
-        float *q = ks + (r * 64 + lane) * 12;
+        const bool in_row = DESC ? p + d <= 15 : p >= d;
+        mat_put(k + 9 * r, A, in_row);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) q[e] = A[e];
-        float P[9];
+        for (int e = 0; e < 9; ++e) T[e] = DESC ? __shfl_down(A[e], d, 64) : __shfl_up(A[e], d, 64);
+        mat_mul(A, T, N);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) P[e] = DESC ? __shfl_down(A[e], d, 64) : __shfl_up(A[e], d, 64);
-        const bool has = DESC ? lane + d < 64 : lane >= d;
-        float N[9];
+        for (int e = 0; e < 9; ++e) A[e] = N[e];
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+        for (int e = 0; e < 9; ++e) T[e] = DESC ? __shfl_down(Q[e], d, 64) : __shfl_up(Q[e], d, 64);
+        mat_mul(Q, T, N);
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-                N[3 * i + j] = fmaf(A[3 * i], P[j], fmaf(A[3 * i + 1], P[3 + j], A[3 * i + 2] * P[6 + j]));
-#pragma unroll
-        for (int e = 0; e < 9; ++e) A[e] = has ? N[e] : A[e];
+        for (int e = 0; e < 9; ++e) Q[e] = in_row ? N[e] : Q[e];
     }
+    mat_put(k + 36, Q, DESC ? (row == 0 || row == 2) : (row == 1 || row == 3));
+    // whole-row product of the row between mine and the source of the last round
+#pragma unroll
+    for (int e = 0; e < 9; ++e) T[e] = __shfl(Q[e], DESC ? 16 : 47, 64);
+    mat_mul(Q, T, N);
+    const bool two_rows = DESC ? row == 0 : row == 3;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Q[e] = two_rows ? N[e] : Q[e];
+    mat_put(k + 45, Q, DESC ? row <= 1 : row >= 2);
 }
+
+__device__ __forceinline__ void ks_round(const float *k, const St &x, St &y)
+{
+    float A[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) A[e] = k[e];
+    mat_acc(A, x, y);
+}
+
+// b: local end state of my chunk; returns the state entering my chunk
+template <bool DESC>
+__device__ __forceinline__ St ks_carry(St b, const float *K, int lane)
+{
+    const float *k = K + lane * kKs;
+    if (!DESC) {
+        ks_round(k + 0, st_dpp<DPP_ROW_SHR + 1, 0xF>(b), b);
+        ks_round(k + 9, st_dpp<DPP_ROW_SHR + 2, 0xF>(b), b);
+        ks_round(k + 18, st_dpp<DPP_ROW_SHR + 4, 0xF>(b), b);
+        ks_round(k + 27, st_dpp<DPP_ROW_SHR + 8, 0xF>(b), b);
+        ks_round(k + 36, st_dpp<DPP_ROW_BCAST15, 0xA>(b), b);
+        ks_round(k + 45, st_dpp<DPP_ROW_BCAST31, 0xC>(b), b);
+        return st_dpp<DPP_WAVE_SHR1, 0xF>(b);
+    }
+    ks_round(k + 0, st_dpp<DPP_ROW_SHL + 1, 0xF>(b), b);
+    ks_round(k + 9, st_dpp<DPP_ROW_SHL + 2, 0xF>(b), b);
+    ks_round(k + 18, st_dpp<DPP_ROW_SHL + 4, 0xF>(b), b);
+    ks_round(k + 27, st_dpp<DPP_ROW_SHL + 8, 0xF>(b), b);
+    const int src = (lane & 16) ? lane : (lane & ~15) + 16;   // rows 0 and 2 take rows 1 and 3
+    ks_round(k + 36, St{__shfl(b.a, src, 64), __shfl(b.b, src, 64), __shfl(b.c, src, 64)}, b);
+    const St u{__int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.a), 32)),
+               __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.b), 32)),
+               __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.c), 32))};
+    ks_round(k + 45, u, b);
+    return st_dpp<DPP_WAVE_SHL1, 0xF>(b);
+}
+
+template <int L>
+constexpr int x_stage_floats() { return 256 * ((L + 3) / 4); }   // whole dwordx4 store rounds
 
 template <int L, bool ADJ>
-__global__ __launch_bounds__(64 * kXWaves) void k_rf3x(const float *in, float *out, const float4 *__restrict__ T,
-                                                        const uint64_t *__restrict__ LM, int nx, int ny,
-                                                        int nplanes, int groups)
+__global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
+    const float *in, float *out, const float4 *__restrict__ T, const uint64_t *__restrict__ LM,
+    const float *__restrict__ PHI, int nx, int ny, int nplanes, int groups)
 {
-    __shared__ __align__(16) float ks[2][6 * 64 * 12];
-    __shared__ float stage[kXWaves][64 * (L + 1)];
+    __shared__ float K[2][64 * kKs];
+    __shared__ __align__(16) float stage[kXWaves][x_stage_floats<L>()];
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // XCD-aware order: consecutive blocks go to different XCDs; all groups of a row
     // land on the same XCD so its coefficients are shared in that XCD's L2.
@@ -268,60 +341,73 @@ __global__ __launch_bounds__(64 * kXWaves) void k_rf3x(const float *in, float *o
     if (row >= ny) return;
     const long plane = (long)nx * ny;
     const int x0 = lane * L;
+    const uint32_t line_bytes = (uint32_t)nx * 4u;
 
     XRow<L, ADJ> R;
-    const float4 *trow = T + (long)row * nx;
+    {
+        const Rsrc tr = make_rsrc(T + (long)row * nx, (uint32_t)nx * 16u);
 #pragma unroll
-    for (int i = 0; i < L; ++i) {
-        const int x = x0 + i;
-        const float4 c = x < nx ? trow[x] : make_float4(0.f, 0.f, 0.f, 0.f);
-        R.kb[i] = c.x;
-        R.kg[i] = c.y;
-        R.k2[i] = c.z;
-        R.k3[i] = c.w;
+        for (int i = 0; i < L; ++i) {
+            const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(tr, (x0 + i) * 16, 0, 0);
+            R.kb[i] = __uint_as_float(c.x);
+            R.kg[i] = __uint_as_float(c.y);
+            R.k2[i] = __uint_as_float(c.z);
+            R.k3[i] = __uint_as_float(c.w);
+        }
     }
     R.lm = LM + (long)row * 3 * XRow<L, ADJ>::LP;
-
-    if (wave == 0) {
+    if (wave < 2) {   // wave 0: ascending scan matrices, wave 1: descending
+        const float *p = PHI + (((long)row * 4 + (ADJ ? 2 : 0) + wave) * 64 + lane) * 12;
         float A[9];
-        R.template transfer<false>(A);
-        ks_build<false>(A, ks[0], lane);
-        R.template transfer<true>(A);
-        ks_build<true>(A, ks[1], lane);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) A[e] = p[e];
+        if (wave == 0) ks_build<false>(A, K[0], lane);
+        else ks_build<true>(A, K[1], lane);
     }
     __syncthreads();
 
     float *stg = stage[wave];
-    for (int ln = grp + groups * wave; ln < nplanes; ln += groups * kXWaves) {
-        const float *src = in + ln * plane + (long)row * nx;
-        float *dst = out + ln * plane + (long)row * nx;
-        float v[L];
+    const int lstep = groups * kXWaves;
+    const int nst = (nx + 255) / 256;   // dwordx4 store rounds per line
+    int ln = grp + groups * wave;
+    float v[L], vn[L];   // the current line, and the next one in flight
+    if (ln < nplanes) chunk_load<L>(make_rsrc(in + (long)ln * plane + (long)row * nx, line_bytes), x0 * 4, vn);
+    for (; ln < nplanes; ln += lstep) {
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const int x = x0 + i;
-            v[i] = x < nx ? src[x] : 0.f;
-        }
+        for (int i = 0; i < L; ++i) v[i] = vn[i];
+        if (ln + lstep < nplanes)
+            chunk_load<L>(make_rsrc(in + (long)(ln + lstep) * plane + (long)row * nx, line_bytes), x0 * 4, vn);
+        {
+            const uint64_t *sp = R.lm + 2 * XRow<L, ADJ>::LP + fresh_int(0);
 #pragma unroll
-        for (int b = 0; b < XRow<L, ADJ>::LP / 8; ++b) {
-            const u32x16 sm = sload16(R.lm + 2 * XRow<L, ADJ>::LP + 8 * b);
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (8 * b + q < L) v[8 * b + q] = zero_if(v[8 * b + q], m64_of(sm, q));
+            for (int i = 0; i < L; ++i) v[i] = zero_if(v[i], sp[i]);   // input only at sea points
         }
         St x{0.f, 0.f, 0.f};
         R.template asc<1>(x, v);
-        x = ks_carry<false>(x, ks[0], lane);
+        x = ks_carry<false>(x, K[0], lane);
         R.template asc<2>(x, v);
         St y{0.f, 0.f, 0.f};
         R.template desc<1>(y, v);
-        y = ks_carry<true>(y, ks[1], lane);
+        y = ks_carry<true>(y, K[1], lane);
         R.template desc<2>(y, v);
-        // stage through LDS (chunk stride L+1 words) and store coalesced
+        // chunk-major into LDS, out in coalesced dwordx4 rounds
 #pragma unroll
-        for (int i = 0; i < L; ++i) stg[lane * (L + 1) + i] = v[i];
+        for (int i = 0; i < L; ++i) stg[x0 + i] = v[i];
         __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS writes done
         __builtin_amdgcn_wave_barrier();
-        for (int k = lane; k < nx; k += 64) dst[k] = stg[(k / L) * (L + 1) + k % L];
+        const Rsrc ro = make_rsrc(out + (long)ln * plane + (long)row * nx, line_bytes);
+#pragma unroll
+        for (int it = 0; it < (L + 3) / 4; ++it) {
+            if (it < nst) {
+                const f4 q = *reinterpret_cast<const f4 *>(stg + 4 * lane + 256 * it);
+                u32x4 w;
+                w.x = __float_as_uint(q.x);
+                w.y = __float_as_uint(q.y);
+                w.z = __float_as_uint(q.z);
+                w.w = __float_as_uint(q.w);
+                __builtin_amdgcn_raw_buffer_store_b128(w, ro, (4 * lane + 256 * it) * 4, 0, 0);
+            }
+        }
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -495,38 +581,25 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float
 }
 
 // ---------------------------------------------------------------- setup
-// Transfer matrices of the y kernel's chunks, FP64 from the FP32 table:
-// PHI[blk][kind][w][j][12], kind 0 forward ascending, 1 forward descending,
-// 2 adjoint ascending, 3 adjoint descending.  One thread per (column, chunk, kind).
-__global__ void k_phi_y(const float4 *__restrict__ T, const uint8_t *__restrict__ code, float *__restrict__ PHI,
-                        int nx, int ny, int L, int nblk)
+// 3x3 transfer matrix of one chunk of n points, FP64 from the FP32 table.
+// kind 0 forward ascending, 1 forward descending, 2 adjoint ascending,
+// 3 adjoint descending.  Forward kinds zero the state before the step at a
+// segment start (0) / end (1); adjoint kinds after the step at a segment end
+// (2) / start (3).  cf(i), cd(i): coefficients and code of chunk point i
+// (ascending position).
+template <class CF, class CD>
+__device__ void chunk_transfer(int kind, int n, CF cf, CD cd, float *dst)
 {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)nblk * kYCols * kYWaves * 4) return;
-    const int j = (int)(t % kYCols);
-    const int w = (int)((t / kYCols) % kYWaves);
-    const int kind = (int)((t / (kYCols * kYWaves)) % 4);
-    const int blk = (int)(t / (kYCols * kYWaves * 4));
-    const int col = blk * kYCols + j;
-    float *dst = PHI + ((((long)blk * 4 + kind) * kYWaves + w) * kYCols + j) * 12;
-    auto cf = [&](int r) -> float4 {
-        return (col < nx && r >= 0 && r < ny) ? T[(long)r * nx + col] : make_float4(0.f, 0.f, 0.f, 0.f);
-    };
-    auto cd = [&](int r) -> uint8_t {
-        return (col < nx && r >= 0 && r < ny) ? code[(long)r * nx + col] : (uint8_t)(CODE_FRESET | CODE_BRESET);
-    };
+    const bool desc = kind & 1;
+    const uint8_t flag = kind == 0 ? CODE_FRESET : kind == 1 ? CODE_BRESET : kind == 2 ? CODE_BRESET : CODE_FRESET;
     double A[9];
     for (int k = 0; k < 3; ++k) {
         double s0 = k == 0, s1 = k == 1, s2 = k == 2;
-        for (int ii = 0; ii < L; ++ii) {
-            const bool desc = kind & 1;
-            const int r = w * L + (desc ? L - 1 - ii : ii);
-            const float4 c = cf(r);
+        for (int ii = 0; ii < n; ++ii) {
+            const int i = desc ? n - 1 - ii : ii;
+            const float4 c = cf(i);
             const double gm = c.y, c2 = c.z, c3 = c.w;
-            // forward kinds: zero before the step at a segment start (0) / end (1);
-            // adjoint kinds: zero after the step at a segment end (2) / start (3)
-            const uint8_t flag = kind == 0 ? CODE_FRESET : kind == 1 ? CODE_BRESET : kind == 2 ? CODE_BRESET : CODE_FRESET;
-            const bool rs = cd(r) & flag;
+            const bool rs = cd(i) & flag;
             if (kind < 2) {
                 if (rs) { s0 = 0; s1 = 0; s2 = 0; }
                 const double tt = -gm * s0 - c2 * s1 - c3 * s2;
@@ -550,16 +623,62 @@ __global__ void k_phi_y(const float4 *__restrict__ T, const uint8_t *__restrict_
     dst[9] = dst[10] = dst[11] = 0.f;
 }
 
+// y kernel's chunks: PHI[blk][kind][w][j][12], one thread per (column, chunk, kind)
+__global__ void k_phi_y(const float4 *__restrict__ T, const uint8_t *__restrict__ code, float *__restrict__ PHI,
+                        int nx, int ny, int L, int nblk)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nblk * kYCols * kYWaves * 4) return;
+    const int j = (int)(t % kYCols);
+    const int w = (int)((t / kYCols) % kYWaves);
+    const int kind = (int)((t / (kYCols * kYWaves)) % 4);
+    const int blk = (int)(t / (kYCols * kYWaves * 4));
+    const int col = blk * kYCols + j;
+    float *dst = PHI + ((((long)blk * 4 + kind) * kYWaves + w) * kYCols + j) * 12;
+    const bool cok = col < nx;
+    auto cf = [&](int i) -> float4 {
+        const int r = w * L + i;
+        return (cok && r < ny) ? T[(long)r * nx + col] : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto cd = [&](int i) -> uint8_t {
+        const int r = w * L + i;
+        return (cok && r < ny) ? code[(long)r * nx + col] : (uint8_t)(CODE_FRESET | CODE_BRESET);
+    };
+    chunk_transfer(kind, L, cf, cd, dst);
+}
+
+// x kernel's chunks: PHI[row][kind][c][12], one thread per (row, kind, chunk)
+__global__ void k_phi_x(const float4 *__restrict__ T, const uint8_t *__restrict__ code, float *__restrict__ PHI,
+                        int nx, int ny, int L)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)ny * 4 * 64) return;
+    const int c = (int)(t % 64);
+    const int kind = (int)((t / 64) % 4);
+    const int row = (int)(t / 256);
+    const float4 *tr = T + (long)row * nx;
+    const uint8_t *cr = code + (long)row * nx;
+    auto cf = [&](int i) -> float4 {
+        const int x = c * L + i;
+        return x < nx ? tr[x] : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto cd = [&](int i) -> uint8_t {
+        const int x = c * L + i;
+        return x < nx ? cr[x] : (uint8_t)(CODE_FRESET | CODE_BRESET);
+    };
+    chunk_transfer(kind, L, cf, cd, PHI + t * 12);
+}
+
 // ---------------------------------------------------------------- dispatch
 template <int L, bool ADJ>
-static hipError_t launch_x(const float *in, float *out, const float4 *T, const uint64_t *LM, int nx, int ny,
-                           int nplanes, hipStream_t st)
+static hipError_t launch_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
+                           int nx, int ny, int nplanes, hipStream_t st)
 {
     // groups per row: enough workgroups to cover the chip several times
     int groups = 1;
     while (groups < 8 && (long)((ny + 7) / 8) * 8 * groups < 2048 && groups * kXWaves * 2 <= nplanes) groups *= 2;
     const unsigned nb = (unsigned)(((ny + 7) / 8) * 8 * groups);
-    k_rf3x<L, ADJ><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, nx, ny, nplanes, groups);
+    k_rf3x<L, ADJ><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups);
     return hipGetLastError();
 }
 
@@ -576,19 +695,20 @@ static hipError_t launch_y(const float *in, float *out, const float4 *T, const u
 
 #define RF_X_CASE(Lv)                                                                                     \
     case Lv:                                                                                              \
-        return adj ? launch_x<Lv, true>(in, out, T, LM, nx, ny, nplanes, st)                              \
-                   : launch_x<Lv, false>(in, out, T, LM, nx, ny, nplanes, st);
+        return adj ? launch_x<Lv, true>(in, out, T, LM, PHI, nx, ny, nplanes, st)                         \
+                   : launch_x<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, st);
 #define RF_Y_CASE(Lv)                                                                                     \
     case Lv:                                                                                              \
         return adj ? launch_y<Lv, true>(in, out, T, LM, PHI, nx, ny, nplanes, st)                         \
                    : launch_y<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, st);
 
-hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, int lx, int nx, int ny,
-                      int nplanes, bool adj, hipStream_t st)
+hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int lx,
+                      int nx, int ny, int nplanes, bool adj, hipStream_t st)
 {
     switch (lx) {
-        RF_X_CASE(1) RF_X_CASE(2) RF_X_CASE(3) RF_X_CASE(4) RF_X_CASE(6) RF_X_CASE(8)
-        RF_X_CASE(12) RF_X_CASE(16) RF_X_CASE(20) RF_X_CASE(24) RF_X_CASE(28) RF_X_CASE(32)
+        RF_X_CASE(1) RF_X_CASE(3) RF_X_CASE(5) RF_X_CASE(7) RF_X_CASE(9) RF_X_CASE(11) RF_X_CASE(13)
+        RF_X_CASE(15) RF_X_CASE(17) RF_X_CASE(19) RF_X_CASE(21) RF_X_CASE(23) RF_X_CASE(25) RF_X_CASE(27)
+        RF_X_CASE(29) RF_X_CASE(31) RF_X_CASE(33)
     default: return hipErrorNotSupported;
     }
 }
@@ -601,6 +721,13 @@ hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const uint64
         RF_Y_CASE(32) RF_Y_CASE(40) RF_Y_CASE(48) RF_Y_CASE(56) RF_Y_CASE(64)
     default: return hipErrorNotSupported;
     }
+}
+
+hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int lx, hipStream_t st)
+{
+    const long n = (long)ny * 4 * 64;
+    k_phi_x<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(T, code, PHI, nx, ny, lx);
+    return hipGetLastError();
 }
 
 hipError_t setup_phi_y(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int ly, hipStream_t st)

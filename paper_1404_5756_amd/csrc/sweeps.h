@@ -19,9 +19,10 @@ hipError_t seq_rf1_f64(const double *in, double *out, const double2 *C, const ui
 
 namespace rf {
 // tiled FP32 kernels (sweep_fast.hip); hipErrorNotSupported when the tile size is not covered
-hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, int lx, int nx, int ny,
-                      int nplanes, bool adj, hipStream_t st);
+hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int lx,
+                      int nx, int ny, int nplanes, bool adj, hipStream_t st);
 hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int ly,
                       int nx, int ny, int nplanes, bool adj, hipStream_t st);
 hipError_t setup_phi_y(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int ly, hipStream_t st);
+hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int lx, hipStream_t st);
 }  // namespace rf

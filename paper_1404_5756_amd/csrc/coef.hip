@@ -213,7 +213,7 @@ __global__ void k_lanemask_x(const uint8_t *__restrict__ code, uint64_t *__restr
 }
 
 // Lane masks of the y kernel: one thread per (mask level, column block, entry e
-// < lys); entry e describes row e-1 and bit j column 32*blk + j; rows and
+// < lys); entry e describes row e-8 and bit j column 64*blk + j; rows and
 // columns outside the grid (and the guard entries) are outside every segment.
 __global__ void k_lanemask_y(const uint8_t *__restrict__ code, uint64_t *__restrict__ lm, int nx, int ny,
                              int nl, int ly)
@@ -221,23 +221,22 @@ __global__ void k_lanemask_y(const uint8_t *__restrict__ code, uint64_t *__restr
     const int nblk = (nx + kYCols - 1) / kYCols, lys = lmy_stride(ly);
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long)nl * nblk * lys) return;
-    const int e = (int)(t % lys), r = e - 1;
+    const int e = (int)(t % lys), r = e - 8;
     const long lb = t / lys;                  // level * nblk + blk
     const int blk = (int)(lb % nblk), lev = (int)(lb / nblk);
-    uint32_t f = 0, b = 0, s = 0;
+    uint64_t f = 0, b = 0, s = 0;
     for (int j = 0; j < kYCols; ++j) {
         const int x = blk * kYCols + j;
         const uint8_t v = (x < nx && r >= 0 && r < ny) ? code[((long)lev * ny + r) * nx + x]
                                                        : (uint8_t)(CODE_FRESET | CODE_BRESET);
-        f |= (uint32_t)((v & CODE_FRESET) != 0) << j;
-        b |= (uint32_t)((v & CODE_BRESET) != 0) << j;
-        s |= (uint32_t)((v & CODE_SEA) != 0) << j;
+        f |= (uint64_t)((v & CODE_FRESET) != 0) << j;
+        b |= (uint64_t)((v & CODE_BRESET) != 0) << j;
+        s |= (uint64_t)((v & CODE_SEA) != 0) << j;
     }
-    // both halves of the wave (two planes) share the column pattern
     uint64_t *o = lm + lb * 3 * lys + e;
-    o[0] = f | ((uint64_t)f << 32);
-    o[lys] = b | ((uint64_t)b << 32);
-    o[2 * lys] = ~(s | ((uint64_t)s << 32));
+    o[0] = f;
+    o[lys] = b;
+    o[2 * lys] = ~s;
 }
 
 bool grid_ok(const rf_grid *g)

@@ -48,8 +48,8 @@ struct BlockHeader {
     // lane-mask tables of the tiled FP32 kernels (0 when the shape is not tiled)
     int32_t lx, ly;           // points per lane along x (64 lanes per row), per wave along y (16 waves)
     uint64_t off_lmx;         // uint64 [mask_nlev][ny][3][lxp]: FRESET, BRESET, not-SEA lane masks, bit c = chunk c
-    uint64_t off_lmy;         // uint64 [mask_nlev][nblk][3][lys]: bits j and 32+j = column 32*blk + j, entry r+1 = row r
-    uint64_t off_phiy;        // float [nblk][4][16][32][12]: y-chunk transfer matrices (2-D mask and sigma only)
+    uint64_t off_lmy;         // uint64 [mask_nlev][nblk][3][lys]: bit j = column 64*blk + j, entry 8+r = row r
+    uint64_t off_phiy;        // float [nblk][4][16][64][12]: y-chunk transfer matrices (2-D mask and sigma only)
     uint64_t off_phix;        // float [ny][4][64][12]: x-chunk transfer matrices (2-D mask and sigma only)
 };
 static_assert(sizeof(BlockHeader) <= 256, "header must fit in 256 bytes");
@@ -58,9 +58,9 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Tiling of the FP32 kernels.  x: one wave per row, 64 lanes each own a chunk
 // of lx consecutive points (lx odd, so that a chunk-major LDS layout is free
-// of bank conflicts).  y: 16 waves per column block, each wave owns a chunk of
-// ly consecutive rows; lanes are 32 columns x 2 planes.
-constexpr int kLxMax = 33, kLyMax = 64, kYWaves = 16, kYCols = 32;
+// of bank conflicts).  y: 16 waves per block of 64 columns, each wave owns a
+// chunk of ly consecutive rows; lane = column, two planes per lane when ly <= 45.
+constexpr int kLxMax = 33, kLyMax = 64, kYWaves = 16, kYCols = 64;
 __host__ __device__ inline int tile_lx(int nx)
 {
     const int need = (nx + 63) / 64;
@@ -69,17 +69,18 @@ __host__ __device__ inline int tile_lx(int nx)
 }
 // padded per-row length of the x lane-mask arrays (whole 8-entry blocks)
 __host__ __device__ inline int lmx_stride(int lx) { return (lx + 7) & ~7; }
-// per-column-block length of the y lane-mask arrays: a guard entry before row 0,
-// 16*ly rows, a guard after, and room for a trailing 8-entry block load
-__host__ __device__ inline int lmy_stride(int ly) { return 16 * ly + 2 + 8; }
+// per-column-block length of the y lane-mask arrays: 8 guard entries before row
+// 0, 16*ly rows (whole 8-entry blocks) and 8 guard entries after
+__host__ __device__ inline int lmy_stride(int ly) { return 16 * ((ly + 7) & ~7) + 16; }
 __host__ __device__ inline int tile_ly(int ny)
 {
     const int need = (ny + kYWaves - 1) / kYWaves;
-    const int opts[] = {2, 4, 8, 12, 16, 24, 32, 40, 48, 56, 64};
+    const int opts[] = {1, 2, 3, 4, 6, 8, 12, 16, 20, 24, 28, 32, 36, 40, 45, 48, 56, 64};
     for (int o : opts)
         if (o >= need) return o;
     return 0;
 }
+__host__ __device__ inline int y_planes_per_lane(int ly) { return ly <= 45 ? 2 : 1; }
 
 // Geometry of one direction's lines inside a [nplanes][ny][nx] field stack.
 struct LineGeom {

@@ -23,6 +23,8 @@
 #include "rf3_internal.h"
 #include "sweeps.h"
 
+#include <type_traits>
+
 namespace rf {
 
 namespace {
@@ -413,170 +415,191 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
 }
 
 // ======================================================================
-// y direction: 16 waves x 64 lanes per workgroup; wave w owns rows
-// [w*L, w*L + L) of 32 columns; lane = (column j = lane & 31, plane h = lane >> 5).
-// The chunk transfer matrices (per column, chunk and sweep) come from the
-// coefficient block; carries pass between waves through LDS.  Coefficients are
-// read from L2 one row at a time through a rolling window of kYWin loads.
+// y direction: 16 waves per block of 64 columns; wave w owns rows
+// [w*L, w*L + L), lane = column, and every lane carries P planes (P = 2 when
+// L <= 45) so that each coefficient load serves P recurrences.  The chunk
+// transfer matrices (per column, chunk and sweep) come from the coefficient
+// block; local end states pass between the waves through LDS.  Coefficients
+// are read one row at a time through a rolling window.  A workgroup loops
+// over the plane groups of its column block.  Row offsets are scalar buffer
+// offsets, clamped to the grid: rows past the end are outside every segment
+// (their input is masked off and they are never stored).
 // ======================================================================
-constexpr int kYWin = 4;
+constexpr int kYWin = 3;
 
-template <int L, bool ADJ>
-struct YCol {
-    static constexpr int LP = (L + 7) & ~7;     // steps covered by whole 8-entry mask blocks
-    const float4 *T;                            // coefficient table (column 0)
-    uint32_t colb;                              // byte offset of this lane's column (clamped into the grid)
-    const uint64_t *lm;                         // this column block's masks [3][lys], entry r+1 = row r
-    int nx, ny, r0, lys;
-    bool colok;
-
-    // rows outside the grid are clamped: their coefficients are never used with a
-    // nonzero state (the masks reset the state there), they only need to be finite
-    // uniform row base + per-lane column offset
-    __device__ __forceinline__ f4 coef(GLOBAL const float4 *Tb, int r) const
-    {
-        GLOBAL const char *row = (GLOBAL const char *)Tb + (long)min(max(r, 0), ny - 1) * nx * 16;
-        return *(GLOBAL const f4 *)(row + colb);
-    }
-    // One pass over the chunk.  DESC: descending rows.  MODE 1: no output,
-    // MODE 2: output into v (DESC also applies the sea mask).
-    template <bool DESC, int MODE>
-    __device__ __forceinline__ void pass(St &x, float *v) const
-    {
-        // ascending uses FRESET (forward: before the step) or BRESET (adjoint: after);
-        // descending uses BRESET (forward) or FRESET (adjoint)
-        const uint64_t *rp = lm + ((ADJ ? !DESC : DESC) ? lys : 0) + 1;
-        GLOBAL const float4 *Tb = fresh(T);
-        const int r0 = fresh_int(this->r0);
-        f4 win[kYWin];
-#pragma unroll
-        for (int q = 0; q < kYWin; ++q) win[q] = coef(Tb, DESC ? r0 + L - 1 - q : r0 + q);
-#pragma unroll
-        for (int bb = 0; bb < LP / 8; ++bb) {
-            const int b = DESC ? LP / 8 - 1 - bb : bb;
-            const u32x16 m = sload16(rp + r0 + 8 * b);
-            u32x16 sm;
-            if (DESC && MODE == 2) sm = sload16(lm + 2 * lys + 1 + r0 + 8 * b);
-#pragma unroll
-            for (int qq = 0; qq < 8; ++qq) {
-                const int q = DESC ? 7 - qq : qq;
-                const int i = 8 * b + q;
-                if (i >= L) continue;
-                const int ii = DESC ? L - 1 - i : i;     // step number within the pass
-                const f4 k = win[ii % kYWin];
-                if (ii + kYWin < L) win[ii % kYWin] = coef(Tb, DESC ? r0 + i - kYWin : r0 + i + kYWin);
-                float o;
-                if (!ADJ) {
-                    st_reset(x, m64_of(m, q));
-                    fwd_step(x, k.x * v[i], k.y, k.z, k.w);
-                    o = x.a;
-                } else {
-                    o = adj_step(x, v[i], k.x, k.y, k.z, k.w);
-                    st_reset(x, m64_of(m, q));
-                }
-                if (MODE == 2) v[i] = (DESC) ? zero_if(o, m64_of(sm, q)) : o;
-                mem_fence_compiler();   // keep the window's loads from being hoisted further
-            }
-        }
-    }
-};
-
-template <int L, bool ADJ>
-__global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float *out,
-                                                         const float4 *__restrict__ T,
+template <int L, bool ADJ, int P>
+__global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float *out, const float4 *T,
                                                          const uint64_t *__restrict__ LM,
-                                                         const float *__restrict__ PHI, int nx, int ny,
-                                                         int nplanes, int nblk, int npairs)
+                                                         const float *__restrict__ PHI, int nx_, int ny_,
+                                                         int nplanes, int nblk, int ngrp)
 {
-    __shared__ __align__(16) float phi[2][kYWaves][kYCols][12];
-    __shared__ float bsh[2][kYWaves][64][3];
+    constexpr int LB = (L + 7) / 8;   // 8-row mask blocks per chunk
+    __shared__ float phi[2][kYWaves][kYCols * 9];
+    __shared__ float bsh[2][kYWaves][P][kYCols * 3];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int j = lane & 31, h = lane >> 5;
+    // XCD-aware order: all plane groups of a column block run on one XCD (shared L2)
     const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
-    // XCD-aware order: all plane pairs of a column block run on one XCD (shared L2)
-    const int blk = (slot / npairs) * 8 + xcd, pr = slot % npairs;
+    const int blk = (slot / ngrp) * 8 + xcd, grp = slot % ngrp;
     if (blk >= nblk) return;
-    const int col = blk * kYCols + j;
-    const long plane = (long)nx * ny;
-    YCol<L, ADJ> C;
-    C.T = T;
-    C.colb = (uint32_t)min(col, nx - 1) * 16u;   // columns past the grid are inactive (masks); any finite value will do
-    C.nx = nx;
-    C.ny = ny;
-    C.r0 = w * L;
-    C.lys = lmy_stride(L);
-    C.colok = col < nx;
-    C.lm = LM + (long)blk * 3 * C.lys;
-
-    // transfer matrices of all chunks of this column block: [sweep][chunk][col][12]
+    const int col = blk * kYCols + lane;
+    const long plane = (long)nx_ * ny_;
+    const int lys = lmy_stride(L);
+    const uint64_t *lm = LM + (long)blk * 3 * lys + 8;   // entry r = row r
     {
         const int k0 = ADJ ? 2 : 0;
-        const float *src = PHI + (long)blk * 4 * kYWaves * kYCols * 12;
-        for (int e = threadIdx.x; e < 2 * kYWaves * kYCols * 12; e += 64 * kYWaves) {
-            const int s = e / (kYWaves * kYCols * 12), rest = e % (kYWaves * kYCols * 12);
-            (&phi[0][0][0][0])[e] = src[(long)(k0 + s) * kYWaves * kYCols * 12 + rest];
+        for (int e = threadIdx.x; e < 2 * kYWaves * kYCols; e += 64 * kYWaves) {
+            const int sw = e / (kYWaves * kYCols), rest = e % (kYWaves * kYCols);
+            const float *src = PHI + (((long)blk * 4 + k0 + sw) * kYWaves * kYCols + rest) * 12;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) phi[sw][rest / kYCols][(rest % kYCols) * 9 + q] = src[q];
         }
     }
+    // columns past the grid: offsets beyond every buffer (loads read 0, stores are dropped)
+    const uint32_t cb = col < nx_ ? (uint32_t)col * 4u : 0x7fffffffu;
+    const uint32_t cbt = col < nx_ ? (uint32_t)col * 16u : 0x7fffffffu;
+    const Rsrc rt = make_rsrc(T, (uint32_t)(plane * 16));
+    const int rowb_ = nx_ * 4;
+    __syncthreads();
 
-    {
-        const int pl = 2 * pr + h;
-        const bool ok = C.colok && pl < nplanes;
-        // lanes without a line read a valid address (their results are never stored)
-        const uint32_t vb = ok ? ((uint32_t)h * (uint32_t)plane + (uint32_t)col) * 4u : 0u;
-        GLOBAL const char *ib = (GLOBAL const char *)fresh(in) + (long)(2 * pr) * plane * 4;
-        float v[L];
+    for (int pg = grp * P; pg < nplanes; pg += ngrp * P) {
+        // opaque per iteration: keeps the per-row offsets and conditions out of the
+        // loop preheader (hoisted, they would be live in SGPRs across the loop)
+        const int r0 = fresh_int(w * L), ny = fresh_int(ny_), rowb = fresh_int(rowb_), nx = fresh_int(nx_);
+        float v[P][L];
+        Rsrc ri[P], ro[P];
 #pragma unroll
-        for (int i = 0; i < L; ++i)
-            v[i] = *(GLOBAL const float *)(ib + (long)min(C.r0 + i, ny - 1) * nx * 4 + vb);
+        for (int p = 0; p < P; ++p) {
+            const int pl = min(pg + p, nplanes - 1);
+            ri[p] = make_rsrc(in + pl * plane, (uint32_t)(plane * 4));
+            ro[p] = make_rsrc(out + pl * plane, pg + p < nplanes ? (uint32_t)(plane * 4) : 0u);
+        }
+        {
+            // running row offset (a chain, so the compiler keeps one of them live)
+            const int last = (ny - 1) * rowb;
+            int roff = fresh_int(min(r0, ny - 1) * rowb);
 #pragma unroll
-        for (int b = 0; b < YCol<L, ADJ>::LP / 8; ++b) {
-            const u32x16 sm = sload16(C.lm + 2 * C.lys + 1 + C.r0 + 8 * b);
+            for (int i = 0; i < L; ++i) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (8 * b + q < L) v[8 * b + q] = zero_if(v[8 * b + q], m64_of(sm, q));
+                for (int p = 0; p < P; ++p)
+                    v[p][i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ri[p], cb, roff, 0));
+                roff = fresh_int(min(roff + rowb, last));
+            }
         }
-        // ---- ascending sweep: local pass, chain over the chunks above, rerun
-        St x{0.f, 0.f, 0.f};
-        C.template pass<false, 1>(x, v);
-        bsh[0][w][lane][0] = x.a;
-        bsh[0][w][lane][1] = x.b;
-        bsh[0][w][lane][2] = x.c;
-        __syncthreads();
-        St c{0.f, 0.f, 0.f};
-        for (int k = 0; k < w; ++k) {
-            const float4 *q = reinterpret_cast<const float4 *>(phi[0][k][j]);
-            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
-            const float A[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
-            St n{bsh[0][k][lane][0], bsh[0][k][lane][1], bsh[0][k][lane][2]};
-            mat_acc(A, c, n);
-            c = n;
-        }
-        x = c;
-        C.template pass<false, 2>(x, v);
-        // ---- descending sweep
-        x = St{0.f, 0.f, 0.f};
-        C.template pass<true, 1>(x, v);
-        bsh[1][w][lane][0] = x.a;
-        bsh[1][w][lane][1] = x.b;
-        bsh[1][w][lane][2] = x.c;
-        __syncthreads();
-        c = St{0.f, 0.f, 0.f};
-        for (int k = kYWaves - 1; k > w; --k) {
-            const float4 *q = reinterpret_cast<const float4 *>(phi[1][k][j]);
-            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
-            const float A[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
-            St n{bsh[1][k][lane][0], bsh[1][k][lane][1], bsh[1][k][lane][2]};
-            mat_acc(A, c, n);
-            c = n;
-        }
-        x = c;
-        C.template pass<true, 2>(x, v);
-        if (ok) {
-            GLOBAL char *ob = (GLOBAL char *)fresh(out) + (long)(2 * pr) * plane * 4;
+        {   // input only at sea points
+            const uint64_t *sp = lm + 2 * lys + r0;
 #pragma unroll
-            for (int i = 0; i < L; ++i)
-                if (C.r0 + i < ny) *(GLOBAL float *)(ob + (long)(C.r0 + i) * nx * 4 + vb) = v[i];
+            for (int b = 0; b < LB; ++b) {
+                const u32x16 m = sload16(sp + 8 * b);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (8 * b + q < L)
+#pragma unroll
+                        for (int p = 0; p < P; ++p) v[p][8 * b + q] = zero_if(v[p][8 * b + q], m64_of(m, q));
+            }
         }
+        // one pass over the chunk for all P planes.  MODE 1: local (no output),
+        // MODE 2: output into v (descending also applies the sea mask).
+        auto pass = [&](St *x, auto DC, auto MC) {
+            constexpr bool desc = decltype(DC)::value;
+            constexpr int mode = decltype(MC)::value;
+            // ascending uses FRESET (forward: before the step) or BRESET (adjoint: after);
+            // descending uses BRESET (forward) or FRESET (adjoint)
+            const uint64_t *rp = lm + ((ADJ ? !desc : desc) ? lys : 0) + r0;
+            const uint64_t *sp = lm + 2 * lys + r0;
+            // byte offset of the next row to fetch, a chain through opaque values so
+            // that the offsets are formed one at a time; clamped at the last row
+            const int crow = nx * 16, clast = (ny - 1) * crow;
+            int cur = fresh_int((desc ? r0 + L - 1 : r0) * crow);
+            auto cload = [&]() -> u32x4 {
+                const u32x4 z = __builtin_amdgcn_raw_buffer_load_b128(rt, cbt, min(cur, clast), 0);
+                cur = fresh_int(cur + (desc ? -crow : crow));
+                return z;
+            };
+            u32x4 win[kYWin];
+#pragma unroll
+            for (int q = 0; q < kYWin; ++q) win[q] = cload();
+#pragma unroll
+            for (int bb = 0; bb < LB; ++bb) {
+                const int b = desc ? LB - 1 - bb : bb;
+                const u32x16 m = sload16(rp + 8 * b);
+                u32x16 sm;
+                if (mode == 2 && desc) sm = sload16(sp + 8 * b);
+#pragma unroll
+                for (int qq = 0; qq < 8; ++qq) {
+                    const int q = desc ? 7 - qq : qq;
+                    const int i = 8 * b + q;
+                    if (i >= L) continue;
+                    const int ii = desc ? L - 1 - i : i;   // step number within the pass
+                    const u32x4 c = win[ii % kYWin];
+                    if (ii + kYWin < L) win[ii % kYWin] = cload();
+                    const float bt = __uint_as_float(c.x), gm = __uint_as_float(c.y);
+                    const float c2 = __uint_as_float(c.z), c3 = __uint_as_float(c.w);
+                    const uint64_t mm = m64_of(m, q);
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        float o;
+                        if (!ADJ) {
+                            st_reset(x[p], mm);
+                            fwd_step(x[p], bt * v[p][i], gm, c2, c3);
+                            o = x[p].a;
+                        } else {
+                            o = adj_step(x[p], v[p][i], bt, gm, c2, c3);
+                            st_reset(x[p], mm);
+                        }
+                        if (mode == 2) v[p][i] = desc ? zero_if(o, m64_of(sm, q)) : o;
+                    }
+                    mem_fence_compiler();   // keep the window's loads from being hoisted further
+                }
+            }
+        };
+        // local pass, chain over the chunks before mine, rerun with the true state
+        auto sweep = [&](auto DC) {
+            constexpr bool desc = decltype(DC)::value;
+            constexpr int sw = desc ? 1 : 0;
+            St x[P];
+#pragma unroll
+            for (int p = 0; p < P; ++p) x[p] = St{0.f, 0.f, 0.f};
+            pass(x, DC, std::integral_constant<int, 1>{});
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                bsh[sw][w][p][lane * 3] = x[p].a;
+                bsh[sw][w][p][lane * 3 + 1] = x[p].b;
+                bsh[sw][w][p][lane * 3 + 2] = x[p].c;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                St c{0.f, 0.f, 0.f};
+                const int k_lo = desc ? w + 1 : 0, k_hi = desc ? kYWaves : w;
+                for (int kk = k_lo; kk < k_hi; ++kk) {
+                    const int k = desc ? k_hi - 1 - (kk - k_lo) : kk;   // nearest chunk last
+                    float A[9];
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) A[e] = phi[sw][k][lane * 9 + e];
+                    St n{bsh[sw][k][p][lane * 3], bsh[sw][k][p][lane * 3 + 1], bsh[sw][k][p][lane * 3 + 2]};
+                    mat_acc(A, c, n);
+                    c = n;
+                }
+                x[p] = c;
+            }
+            pass(x, DC, std::integral_constant<int, 2>{});
+        };
+        sweep(std::false_type{});
+        sweep(std::true_type{});
+        {
+            const int lim = ny * rowb;
+            int roff = fresh_int(r0 * rowb);
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                if (roff < lim) {   // rows past the grid are not stored
+#pragma unroll
+                    for (int p = 0; p < P; ++p)
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[p][i]), ro[p], cb, roff, 0);
+                }
+                roff = fresh_int(roff + rowb);
+            }
+        }
+        __syncthreads();   // bsh is rewritten by the next plane group
     }
 }
 
@@ -682,14 +705,40 @@ static hipError_t launch_x(const float *in, float *out, const float4 *T, const u
     return hipGetLastError();
 }
 
+// compute units of the current device (cached per device)
+static int cu_count()
+{
+    static int cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
 template <int L, bool ADJ>
 static hipError_t launch_y(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
                            int nx, int ny, int nplanes, hipStream_t st)
 {
+    constexpr int P = (L <= 45) ? 2 : 1;
+    static_assert(P == 1 || P == 2, "planes per lane");
     const int nblk = (nx + kYCols - 1) / kYCols;
-    const int npairs = (nplanes + 1) / 2;
-    const unsigned nb = (unsigned)(((nblk + 7) / 8) * 8 * npairs);
-    k_rf3y<L, ADJ><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, nblk, npairs);
+    const int npg = (nplanes + P - 1) / P;   // plane groups
+    // groups per column block: one workgroup per CU at a time, so minimise
+    // (rounds of workgroups) x (plane groups per workgroup)
+    const int cus = cu_count(), nb8 = ((nblk + 7) / 8) * 8;
+    int best = 1;
+    long best_cost = -1;
+    for (int g = 1; g <= npg; ++g) {
+        const long rounds = ((long)nb8 * g + cus - 1) / cus;
+        const long cost = rounds * ((npg + g - 1) / g);
+        if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = g; }
+    }
+    const unsigned nb = (unsigned)(nb8 * best);
+    k_rf3y<L, ADJ, P><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, nblk, best);
     return hipGetLastError();
 }
 
@@ -716,9 +765,12 @@ hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64
 hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int ly,
                       int nx, int ny, int nplanes, bool adj, hipStream_t st)
 {
+    // scalar row offsets into the coefficient table are 32-bit
+    if ((long)nx * ny * 16 >= (1L << 31)) return hipErrorNotSupported;
     switch (ly) {
-        RF_Y_CASE(2) RF_Y_CASE(4) RF_Y_CASE(8) RF_Y_CASE(12) RF_Y_CASE(16) RF_Y_CASE(24)
-        RF_Y_CASE(32) RF_Y_CASE(40) RF_Y_CASE(48) RF_Y_CASE(56) RF_Y_CASE(64)
+        RF_Y_CASE(1) RF_Y_CASE(2) RF_Y_CASE(3) RF_Y_CASE(4) RF_Y_CASE(6) RF_Y_CASE(8) RF_Y_CASE(12)
+        RF_Y_CASE(16) RF_Y_CASE(20) RF_Y_CASE(24) RF_Y_CASE(28) RF_Y_CASE(32) RF_Y_CASE(36) RF_Y_CASE(40)
+        RF_Y_CASE(45) RF_Y_CASE(48) RF_Y_CASE(56) RF_Y_CASE(64)
     default: return hipErrorNotSupported;
     }
 }

@@ -44,6 +44,11 @@ CASES = [
     (7, 90, 1, 1, 0.2, 3, "fit", False, False, (2.0, 5.0)),
     (8, 260, 517, 2, 0.3, 4, "fit", True, True, (1.5, 12.0)),
     (9, 129, 1100, 1, 0.3, 4, "fit", False, False, (2.0, 12.0)),
+    # tile edges: y chunks of 45 rows (two planes per lane, odd plane count),
+    # y chunks of 56 rows (one plane per lane), x chunks of 33 points
+    (10, 720, 150, 3, 0.3, 4, "fit", False, False, (2.0, 12.0)),
+    (11, 801, 70, 3, 0.3, 4, "fit", False, False, (1.5, 12.0)),
+    (12, 20, 2100, 1, 0.3, 4, "fit", False, False, (1.5, 12.0)),
 ]
 
 

@@ -127,24 +127,36 @@ int rf3_apply_dir(const rf_grid *g, const void *coef, rf_prec prec, int32_t dir,
 int rf1_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, int32_t K,
                  const void *in, void *out, int32_t nlev, int32_t nfields, void *stream);
 
-/* Many independent fields on possibly different grids, processed by one
- * launch per direction (T and S on every level of several grids; the paper's
- * global configuration spreads levels over OpenMP threads, Sec. 5.1).
- * Each item applies rf3_apply_xy (adjoint = 0) or rf3_adjoint_xy
- * (adjoint = 1) to its own nfields fields over all g->nlev levels of its grid.
+/* Many independent fields on possibly different grids in one pass (T and S
+ * on every level of several grids: the paper runs the levels of its global
+ * configuration in parallel, Sec. 5.1).  Each item applies rf3_apply_xy
+ * (adjoint = 0) or rf3_adjoint_xy (adjoint = 1) to its own nfields fields over
+ * all g->nlev levels of its grid.
+ *
+ * The x rows and y column blocks of all items form one work list; it runs as
+ * one persistent work-list launch per (direction, tile size) -- a handful of
+ * launches for any number of items.  Items whose mask or sigma vary with
+ * level (mask_nlev or sigma_nlev > 1) run the line-sequential path instead.
  *
  * Two steps, so that the apply step can be captured into a hipGraph:
- *   1. rf3_batch_plan (host only, no HIP call) writes the work list for the
- *      items into host memory `plan` of rf3_batch_plan_bytes(items, n) bytes;
- *      the caller copies those bytes to device memory it owns;
- *   2. rf3_apply_batch reads that device copy (`plan_dev`) and enqueues the
- *      work.  The same device plan serves any number of calls as long as the
- *      items (pointers, grids, field counts) are unchanged.
- * Only RF_FP32.  Items must not overlap each other's outputs. */
+ *   1. rf3_batch_plan (host only, no HIP call) writes the work list into host
+ *      memory `plan` of exactly rf3_batch_plan_bytes(items, n) bytes (0 when
+ *      the items are invalid); the caller copies those bytes to device memory
+ *      it owns, 256-byte aligned.  The plan records the items' device
+ *      pointers: rebuild it when any item changes.
+ *   2. rf3_apply_batch re-derives the same work list on the host (to know the
+ *      launches), then enqueues them on `stream` reading `plan_dev`.  It
+ *      neither allocates nor synchronises; `plan_bytes` must equal
+ *      rf3_batch_plan_bytes(items, n).  Passing a plan built from other items
+ *      is undefined.
+ * RF_FP32 uses the batched kernels; RF_FP64 applies the items one by one
+ * (plan_dev is then not read and may be NULL).  Items must not overlap each
+ * other's buffers.  Errors: as for rf3_apply_xy, per item; RF_E_ARG for a
+ * wrong plan size or alignment. */
 typedef struct {
     const rf_grid *g;       /* host pointer to the item's grid */
     const void *coef;       /* device: its coefficient block */
-    const void *in;         /* device: [nfields][g->nlev][ny][nx] FP32 */
+    const void *in;         /* device: [nfields][g->nlev][ny][nx] */
     void *out;              /* device: same shape; may equal in */
     int32_t nfields;
 } rf_batch_item;

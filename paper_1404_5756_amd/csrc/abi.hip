@@ -26,8 +26,10 @@ LineGeom geom(const rf_grid *g, int dir, int nlev, int nfields)
     return G;
 }
 
-int check_apply(const rf_grid *g, const void *coef, int prec, const void *in, const void *out,
-                int nlev, int nfields)
+}  // namespace
+
+int rf::check_apply(const rf_grid *g, const void *coef, int prec, const void *in, const void *out,
+                    int nlev, int nfields)
 {
     if (!g || !coef || !in || !out) return RF_E_ARG;
     if (prec != RF_FP32 && prec != RF_FP64) return RF_E_ARG;
@@ -45,21 +47,23 @@ int check_apply(const rf_grid *g, const void *coef, int prec, const void *in, co
     return RF_OK;
 }
 
+namespace {
+
 template <class T>
 const T *tab(const void *coef, uint64_t off)
 {
     return reinterpret_cast<const T *>(reinterpret_cast<const char *>(coef) + off);
 }
 
+}  // namespace
+
 // RF3_SEQUENTIAL=1 in the environment selects the line-sequential FP32 kernels
 // (a cross-check of the tiled kernels); read at every call.
-bool force_sequential()
+bool rf::force_sequential()
 {
     const char *e = getenv("RF3_SEQUENTIAL");
     return e && e[0] == '1';
 }
-
-}  // namespace
 
 // One direction of the 3rd-RF in FP32 (forward when adj is false).  The tiled
 // kernels need one 2-D mask and 2-D sigma for all levels; other cases run the
@@ -95,8 +99,8 @@ static hipError_t rf3_dir(const rf_grid *g, const BlockHeader &h, const void *co
                        tab<uint8_t>(coef, h.off_code[dir]), geom(g, dir, nlev, nfields), adj, st);
 }
 
-static int rf3_run(const rf_grid *g, const void *coef, rf_prec prec, const void *in, void *out,
-                   int32_t nlev, int32_t nfields, void *stream, bool adj)
+int rf::rf3_run(const rf_grid *g, const void *coef, rf_prec prec, const void *in, void *out,
+                int32_t nlev, int32_t nfields, void *stream, bool adj)
 {
     const int rc = check_apply(g, coef, prec, in, out, nlev, nfields);
     if (rc) return rc;

@@ -80,7 +80,23 @@ __host__ __device__ inline int tile_ly(int ny)
         if (o >= need) return o;
     return 0;
 }
-__host__ __device__ inline int y_planes_per_lane(int ly) { return ly <= 45 ? 2 : 1; }
+__host__ __device__ constexpr int y_planes_per_lane(int ly) { return ly <= 45 ? 2 : 1; }
+
+// Batched FP32 application (batch.hip builds these on the host).  One entry per
+// item with its buffers and the tables of both directions; one unit per
+// workgroup: x {item, row, group, groups}, y {item, column block, first plane
+// group, end plane group}; item < 0 marks an idle unit.
+struct BatchEntry {
+    const float *in;
+    float *out;
+    const float4 *T[2];
+    const uint64_t *LM[2];
+    const float *PHI[2];
+    int32_t nx, ny, nplanes, pad;
+};
+struct BatchUnit {
+    int32_t item, a, b, c;
+};
 
 // Geometry of one direction's lines inside a [nplanes][ny][nx] field stack.
 struct LineGeom {

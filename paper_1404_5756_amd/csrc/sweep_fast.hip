@@ -55,6 +55,10 @@ __device__ __forceinline__ void mem_fence_compiler() { asm volatile("" ::: "memo
 // p unchanged, but opaque to the optimiser: addresses derived from it in
 // different passes are not merged and kept live across the passes
 #define GLOBAL __attribute__((address_space(1)))
+// read-only tables read with scalar loads: constant address space
+#define CONST_AS __attribute__((address_space(4)))
+typedef const CONST_AS uint64_t *mask_ptr;
+__device__ __forceinline__ mask_ptr as_const(const uint64_t *p) { return (mask_ptr)p; }
 template <class T>
 __device__ __forceinline__ GLOBAL T *fresh(T *p)
 {
@@ -66,6 +70,18 @@ __device__ __forceinline__ int fresh_int(int v)
 {
     asm volatile("" : "+s"(v));
     return v;
+}
+
+// a wave-uniform value read from memory, as a scalar (the compiler cannot always
+// prove that such loads are uniform)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <class T>
+__device__ __forceinline__ T *uni(T *p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T *>(((uint64_t)hi << 32) | lo);
 }
 
 // mask q of a block of eight 64-bit masks
@@ -164,7 +180,7 @@ template <int L, bool ADJ>
 struct XRow {
     static constexpr int LP = (L + 7) & ~7;   // mask array length (whole 8-blocks)
     float kb[L], kg[L], k2[L], k3[L];          // beta, gamma, c2, c3 of my chunk's points
-    const uint64_t *lm;                        // this row's masks: [3][LP] FRESET, BRESET, not-SEA
+    mask_ptr lm;                               // this row's masks: [3][LP] FRESET, BRESET, not-SEA
 
     // ascending sweep over my chunk.  MODE 1: input v, no output;
     // MODE 2: input v, output written back into v.
@@ -173,7 +189,7 @@ struct XRow {
     {
         // forward: zero the state before a segment start; adjoint: after a segment end.
         // The opaque zero keeps this pass's mask loads inside the pass.
-        const uint64_t *rp = lm + (ADJ ? LP : 0) + fresh_int(0);
+        mask_ptr rp = lm + (ADJ ? LP : 0) + fresh_int(0);
 #pragma unroll
         for (int i = 0; i < L; ++i) {
             const uint64_t m = rp[i];
@@ -194,8 +210,8 @@ struct XRow {
     {
         // forward: zero the state before a segment end; adjoint: after a segment start
         const int z = fresh_int(0);
-        const uint64_t *rp = lm + (ADJ ? 0 : LP) + z;
-        const uint64_t *sp = lm + 2 * LP + z;
+        mask_ptr rp = lm + (ADJ ? 0 : LP) + z;
+        mask_ptr sp = lm + 2 * LP + z;
 #pragma unroll
         for (int i = L - 1; i >= 0; --i) {
             const uint64_t m = rp[i];
@@ -328,19 +344,14 @@ __device__ __forceinline__ St ks_carry(St b, const float *K, int lane)
 template <int L>
 constexpr int x_stage_floats() { return 256 * ((L + 3) / 4); }   // whole dwordx4 store rounds
 
+// Lines of one row: planes grp, grp + groups, ... (4 waves, interleaved).
+// K: [2][64 * kKs] scan matrices, stage: this wave's LDS staging area.
 template <int L, bool ADJ>
-__global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
-    const float *in, float *out, const float4 *__restrict__ T, const uint64_t *__restrict__ LM,
-    const float *__restrict__ PHI, int nx, int ny, int nplanes, int groups)
+__device__ __forceinline__ void x_rows(const float *in, float *out, const float4 *T, const uint64_t *LM,
+                                       const float *PHI, int nx, int ny, int nplanes, int row, int grp,
+                                       int groups, float *K, float *stg)
 {
-    __shared__ float K[2][64 * kKs];
-    __shared__ __align__(16) float stage[kXWaves][x_stage_floats<L>()];
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // XCD-aware order: consecutive blocks go to different XCDs; all groups of a row
-    // land on the same XCD so its coefficients are shared in that XCD's L2.
-    const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
-    const int row = (slot / groups) * 8 + xcd, grp = slot % groups;
-    if (row >= ny) return;
     const long plane = (long)nx * ny;
     const int x0 = lane * L;
     const uint32_t line_bytes = (uint32_t)nx * 4u;
@@ -357,18 +368,17 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
             R.k3[i] = __uint_as_float(c.w);
         }
     }
-    R.lm = LM + (long)row * 3 * XRow<L, ADJ>::LP;
+    R.lm = as_const(LM + (long)row * 3 * XRow<L, ADJ>::LP);
     if (wave < 2) {   // wave 0: ascending scan matrices, wave 1: descending
         const float *p = PHI + (((long)row * 4 + (ADJ ? 2 : 0) + wave) * 64 + lane) * 12;
         float A[9];
 #pragma unroll
         for (int e = 0; e < 9; ++e) A[e] = p[e];
-        if (wave == 0) ks_build<false>(A, K[0], lane);
-        else ks_build<true>(A, K[1], lane);
+        if (wave == 0) ks_build<false>(A, K, lane);
+        else ks_build<true>(A, K + 64 * kKs, lane);
     }
     __syncthreads();
 
-    float *stg = stage[wave];
     const int lstep = groups * kXWaves;
     const int nst = (nx + 255) / 256;   // dwordx4 store rounds per line
     int ln = grp + groups * wave;
@@ -380,17 +390,17 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
         if (ln + lstep < nplanes)
             chunk_load<L>(make_rsrc(in + (long)(ln + lstep) * plane + (long)row * nx, line_bytes), x0 * 4, vn);
         {
-            const uint64_t *sp = R.lm + 2 * XRow<L, ADJ>::LP + fresh_int(0);
+            mask_ptr sp = R.lm + 2 * XRow<L, ADJ>::LP + fresh_int(0);
 #pragma unroll
             for (int i = 0; i < L; ++i) v[i] = zero_if(v[i], sp[i]);   // input only at sea points
         }
         St x{0.f, 0.f, 0.f};
         R.template asc<1>(x, v);
-        x = ks_carry<false>(x, K[0], lane);
+        x = ks_carry<false>(x, K, lane);
         R.template asc<2>(x, v);
         St y{0.f, 0.f, 0.f};
         R.template desc<1>(y, v);
-        y = ks_carry<true>(y, K[1], lane);
+        y = ks_carry<true>(y, K + 64 * kKs, lane);
         R.template desc<2>(y, v);
         // chunk-major into LDS, out in coalesced dwordx4 rounds
 #pragma unroll
@@ -414,6 +424,39 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
     }
 }
 
+template <int L, bool ADJ>
+__global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
+    const float *in, float *out, const float4 *__restrict__ T, const uint64_t *__restrict__ LM,
+    const float *__restrict__ PHI, int nx, int ny, int nplanes, int groups)
+{
+    __shared__ float K[2 * 64 * kKs];
+    __shared__ __align__(16) float stage[kXWaves][x_stage_floats<L>()];
+    // XCD-aware order: consecutive blocks go to different XCDs; all groups of a row
+    // land on the same XCD so its coefficients are shared in that XCD's L2.
+    const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
+    const int row = (slot / groups) * 8 + xcd, grp = slot % groups;
+    if (row >= ny) return;
+    x_rows<L, ADJ>(in, out, T, LM, PHI, nx, ny, nplanes, row, grp, groups, K,
+                   stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+}
+
+// Batched form: one workgroup per work unit {item, row, group, groups}; the
+// second pass of a V_H application reads the first pass's output (src_out).
+template <int L, bool ADJ>
+__global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x_batch(
+    const BatchEntry *__restrict__ E, const BatchUnit *__restrict__ U, int src_out)
+{
+    __shared__ float K[2 * 64 * kKs];
+    __shared__ __align__(16) float stage[kXWaves][x_stage_floats<L>()];
+    const BatchUnit *up = U + blockIdx.x;
+    const int item = uni(up->item);
+    if (item < 0) return;
+    const BatchEntry *e = E + item;
+    x_rows<L, ADJ>(uni(src_out ? (const float *)e->out : e->in), uni(e->out), uni(e->T[0]), uni(e->LM[0]),
+                   uni(e->PHI[0]), uni(e->nx), uni(e->ny), uni(e->nplanes), uni(up->a), uni(up->b), uni(up->c), K,
+                   stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+}
+
 // ======================================================================
 // y direction: 16 waves per block of 64 columns; wave w owns rows
 // [w*L, w*L + L), lane = column, and every lane carries P planes (P = 2 when
@@ -427,20 +470,16 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
 // ======================================================================
 constexpr int kYWin = 3;
 
+// One column block: plane groups g0, g0 + gstep, ... below g1 (group g = planes
+// P*g .. P*g + P-1).  phi: [2][16][64 * 9], bsh: [2][16][P][64 * 3] in LDS.
 template <int L, bool ADJ, int P>
-__global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float *out, const float4 *T,
-                                                         const uint64_t *__restrict__ LM,
-                                                         const float *__restrict__ PHI, int nx_, int ny_,
-                                                         int nplanes, int nblk, int ngrp)
+__device__ __forceinline__ void y_block(const float *in, float *out, const float4 *T, const uint64_t *LM,
+                                        const float *PHI, int nx_, int ny_, int nplanes, int blk, int g0,
+                                        int gstep, int g1, float (*phi)[kYWaves][kYCols * 9],
+                                        float (*bsh)[kYWaves][P][kYCols * 3])
 {
     constexpr int LB = (L + 7) / 8;   // 8-row mask blocks per chunk
-    __shared__ float phi[2][kYWaves][kYCols * 9];
-    __shared__ float bsh[2][kYWaves][P][kYCols * 3];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // XCD-aware order: all plane groups of a column block run on one XCD (shared L2)
-    const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
-    const int blk = (slot / ngrp) * 8 + xcd, grp = slot % ngrp;
-    if (blk >= nblk) return;
     const int col = blk * kYCols + lane;
     const long plane = (long)nx_ * ny_;
     const int lys = lmy_stride(L);
@@ -461,7 +500,7 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float
     const int rowb_ = nx_ * 4;
     __syncthreads();
 
-    for (int pg = grp * P; pg < nplanes; pg += ngrp * P) {
+    for (int pg = g0 * P; pg < g1 * P && pg < nplanes; pg += gstep * P) {
         // opaque per iteration: keeps the per-row offsets and conditions out of the
         // loop preheader (hoisted, they would be live in SGPRs across the loop)
         const int r0 = fresh_int(w * L), ny = fresh_int(ny_), rowb = fresh_int(rowb_), nx = fresh_int(nx_);
@@ -603,6 +642,37 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float
     }
 }
 
+template <int L, bool ADJ, int P>
+__global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float *out, const float4 *T,
+                                                         const uint64_t *__restrict__ LM,
+                                                         const float *__restrict__ PHI, int nx, int ny,
+                                                         int nplanes, int nblk, int ngrp)
+{
+    __shared__ float phi[2][kYWaves][kYCols * 9];
+    __shared__ float bsh[2][kYWaves][P][kYCols * 3];
+    // XCD-aware order: all plane groups of a column block run on one XCD (shared L2)
+    const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
+    const int blk = (slot / ngrp) * 8 + xcd, grp = slot % ngrp;
+    if (blk >= nblk) return;
+    y_block<L, ADJ, P>(in, out, T, LM, PHI, nx, ny, nplanes, blk, grp, ngrp, (nplanes + P - 1) / P, phi, bsh);
+}
+
+// Batched form: one workgroup per work unit {item, column block, first and end plane group}.
+template <int L, bool ADJ, int P>
+__global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_batch(const BatchEntry *__restrict__ E,
+                                                               const BatchUnit *__restrict__ U, int src_out)
+{
+    __shared__ float phi[2][kYWaves][kYCols * 9];
+    __shared__ float bsh[2][kYWaves][P][kYCols * 3];
+    const BatchUnit *up = U + blockIdx.x;
+    const int item = uni(up->item);
+    if (item < 0) return;
+    const BatchEntry *e = E + item;
+    y_block<L, ADJ, P>(uni(src_out ? (const float *)e->out : e->in), uni(e->out), uni(e->T[1]), uni(e->LM[1]),
+                       uni(e->PHI[1]), uni(e->nx), uni(e->ny), uni(e->nplanes), uni(up->a), uni(up->b), 1, uni(up->c),
+                       phi, bsh);
+}
+
 // ---------------------------------------------------------------- setup
 // 3x3 transfer matrix of one chunk of n points, FP64 from the FP32 table.
 // kind 0 forward ascending, 1 forward descending, 2 adjoint ascending,
@@ -693,13 +763,22 @@ __global__ void k_phi_x(const float4 *__restrict__ T, const uint8_t *__restrict_
 }
 
 // ---------------------------------------------------------------- dispatch
+// groups per row for the x kernel: enough workgroups to cover the chip several
+// times, at least two lines per wave
+int x_groups(int ny, int nplanes)
+{
+    int groups = 1;
+    while (groups < 8 && (long)((ny + 7) / 8) * 8 * groups < 2048 && groups * kXWaves * 2 <= nplanes) groups *= 2;
+    return groups;
+}
+
+int y_planes_per_unit_group(int ly) { return y_planes_per_lane(ly); }
+
 template <int L, bool ADJ>
 static hipError_t launch_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
                            int nx, int ny, int nplanes, hipStream_t st)
 {
-    // groups per row: enough workgroups to cover the chip several times
-    int groups = 1;
-    while (groups < 8 && (long)((ny + 7) / 8) * 8 * groups < 2048 && groups * kXWaves * 2 <= nplanes) groups *= 2;
+    const int groups = x_groups(ny, nplanes);
     const unsigned nb = (unsigned)(((ny + 7) / 8) * 8 * groups);
     k_rf3x<L, ADJ><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups);
     return hipGetLastError();
@@ -723,7 +802,7 @@ template <int L, bool ADJ>
 static hipError_t launch_y(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
                            int nx, int ny, int nplanes, hipStream_t st)
 {
-    constexpr int P = (L <= 45) ? 2 : 1;
+    constexpr int P = y_planes_per_lane(L);
     static_assert(P == 1 || P == 2, "planes per lane");
     const int nblk = (nx + kYCols - 1) / kYCols;
     const int npg = (nplanes + P - 1) / P;   // plane groups
@@ -771,6 +850,41 @@ hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const uint64
         RF_Y_CASE(1) RF_Y_CASE(2) RF_Y_CASE(3) RF_Y_CASE(4) RF_Y_CASE(6) RF_Y_CASE(8) RF_Y_CASE(12)
         RF_Y_CASE(16) RF_Y_CASE(20) RF_Y_CASE(24) RF_Y_CASE(28) RF_Y_CASE(32) RF_Y_CASE(36) RF_Y_CASE(40)
         RF_Y_CASE(45) RF_Y_CASE(48) RF_Y_CASE(56) RF_Y_CASE(64)
+    default: return hipErrorNotSupported;
+    }
+}
+
+#define RF_XB_CASE(Lv)                                                                                    \
+    case Lv:                                                                                              \
+        if (adj) k_rf3x_batch<Lv, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);                  \
+        else k_rf3x_batch<Lv, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);                     \
+        return hipGetLastError();
+#define RF_YB_CASE(Lv)                                                                                    \
+    case Lv:                                                                                              \
+        if (adj) k_rf3y_batch<Lv, true, y_planes_per_lane(Lv)><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out); \
+        else k_rf3y_batch<Lv, false, y_planes_per_lane(Lv)><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out);   \
+        return hipGetLastError();
+
+hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int lx, bool adj, bool src_out,
+                            hipStream_t st)
+{
+    if (nunits <= 0) return hipSuccess;
+    switch (lx) {
+        RF_XB_CASE(1) RF_XB_CASE(3) RF_XB_CASE(5) RF_XB_CASE(7) RF_XB_CASE(9) RF_XB_CASE(11) RF_XB_CASE(13)
+        RF_XB_CASE(15) RF_XB_CASE(17) RF_XB_CASE(19) RF_XB_CASE(21) RF_XB_CASE(23) RF_XB_CASE(25) RF_XB_CASE(27)
+        RF_XB_CASE(29) RF_XB_CASE(31) RF_XB_CASE(33)
+    default: return hipErrorNotSupported;
+    }
+}
+
+hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int ly, bool adj, bool src_out,
+                            hipStream_t st)
+{
+    if (nunits <= 0) return hipSuccess;
+    switch (ly) {
+        RF_YB_CASE(1) RF_YB_CASE(2) RF_YB_CASE(3) RF_YB_CASE(4) RF_YB_CASE(6) RF_YB_CASE(8) RF_YB_CASE(12)
+        RF_YB_CASE(16) RF_YB_CASE(20) RF_YB_CASE(24) RF_YB_CASE(28) RF_YB_CASE(32) RF_YB_CASE(36) RF_YB_CASE(40)
+        RF_YB_CASE(45) RF_YB_CASE(48) RF_YB_CASE(56) RF_YB_CASE(64)
     default: return hipErrorNotSupported;
     }
 }

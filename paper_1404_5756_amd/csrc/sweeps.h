@@ -7,6 +7,14 @@ namespace rf {
 bool grid_ok(const rf_grid *g);
 BlockHeader layout(const rf_grid *g);
 
+// abi.hip: argument checks shared by the entry points, the RF3_SEQUENTIAL switch,
+// and one whole V_H (or adjoint) application of one grid on a stream
+int check_apply(const rf_grid *g, const void *coef, int prec, const void *in, const void *out, int nlev,
+                int nfields);
+bool force_sequential();
+int rf3_run(const rf_grid *g, const void *coef, rf_prec prec, const void *in, void *out, int32_t nlev,
+            int32_t nfields, void *stream, bool adj);
+
 // line-sequential kernels (sweep_seq.hip)
 hipError_t seq_rf3_f32(const float *in, float *out, const float4 *T1, const float4 *T2,
                        const uint8_t *code, const LineGeom &G, bool adj, hipStream_t st);
@@ -23,6 +31,13 @@ hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64
                       int nx, int ny, int nplanes, bool adj, hipStream_t st);
 hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int ly,
                       int nx, int ny, int nplanes, bool adj, hipStream_t st);
+// batched forms over a work list (all units of one launch share the tile size)
+hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int lx, bool adj, bool src_out,
+                            hipStream_t st);
+hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int ly, bool adj, bool src_out,
+                            hipStream_t st);
+int x_groups(int ny, int nplanes);
+int y_planes_per_unit_group(int ly);
 hipError_t setup_phi_y(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int ly, hipStream_t st);
 hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int lx, hipStream_t st);
 }  // namespace rf

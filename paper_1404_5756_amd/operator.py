@@ -95,3 +95,36 @@ class HorizontalCovariance:
         rf3.rf1_apply_xy(self.grid, self.coef, self._prec(x), self.grid.k1 if K is None else K, x, out,
                          nl, nf, stream)
         return out
+
+
+class Batch:
+    """Several (operator, input, output) items applied together (rf3_apply_batch).
+
+    items: [(HorizontalCovariance, x, y)] with x, y FP32 device tensors
+    [nfields][op.nlev][ny][nx] (y may be x).  The work list is built once here
+    and kept on the device; build a new Batch when any tensor changes.
+    """
+
+    def __init__(self, items, device=None):
+        self._items = []
+        self._keep = []
+        for op, x, y in items:
+            if x.dtype != torch.float32 or y.dtype != torch.float32:
+                raise TypeError("batched fields must be float32")
+            if x.dim() != 4 or tuple(x.shape[1:]) != (op.nlev, op.ny, op.nx) or x.shape != y.shape:
+                raise ValueError(f"expected [nfields][{op.nlev}][{op.ny}][{op.nx}], got {tuple(x.shape)}")
+            if not (x.is_contiguous() and y.is_contiguous()):
+                raise ValueError("batched fields must be contiguous")
+            self._items.append((op.grid, op.coef, x, y, x.shape[0]))
+            self._keep.append((op, x, y))
+        host = rf3.rf3_batch_plan(self._items)
+        dev = device if device is not None else self._items[0][2].device
+        # torch's caching allocator returns 512-byte aligned blocks
+        self.plan = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(dev)
+
+    @property
+    def points(self):
+        return sum(x.numel() for _, x, _ in self._keep)
+
+    def apply(self, adjoint=False, stream=None):
+        rf3.rf3_apply_batch(self._items, rf3.RF_FP32, int(bool(adjoint)), self.plan, self.plan.numel(), stream)

@@ -166,6 +166,34 @@ int rf3_batch_plan(const rf_batch_item *items, int32_t n, void *plan, size_t pla
 int rf3_apply_batch(const rf_batch_item *items, int32_t n, rf_prec prec, int32_t adjoint,
                     const void *plan_dev, size_t plan_bytes, void *stream);
 
+/* 3D-VAR harness: bilinear observation operator H and its adjoint H^T.
+ * The minimiser of Sec. 2 needs V and V^T (above) and the observation
+ * operator with its transpose in every iteration.  Observation o is at level
+ * lev[o] (0 <= lev < g->nlev) and position (x[o], y[o]) in grid units
+ * (0 <= x <= nx-1, 0 <= y <= ny-1); it reads the 4 surrounding points of one
+ * level with bilinear weights.  The field is one [g->nlev][ny][nx] stack.
+ *
+ *   rf_obs_plan_bytes / rf_obs_plan: host only (no HIP call).  Build the
+ *     gather tables into host memory `plan` of exactly the returned size (0 on
+ *     error: invalid grid, nobs < 1, a position outside the grid); *nuniq_out
+ *     receives the number of distinct grid points touched.  The caller copies
+ *     the plan to device memory it owns (256-byte aligned).
+ *   rf_obs_apply:   obs[o] = sum_c w[o][c] field[p[o][c]]  (H field)
+ *   rf_obs_adjoint: field = H^T obs, every point written (0 where no
+ *     observation reads it).  Deterministic: each point sums its entries in
+ *     observation order, without atomics.
+ * nobs, nuniq and npts = nx*ny*nlev must be the plan's; otherwise the kernels
+ * read nothing (and rf_obs_adjoint leaves a zero field).  Asynchronous on
+ * `stream`, no allocation; obs and field are device arrays of `prec`. */
+size_t rf_obs_plan_bytes(const rf_grid *g, int32_t nobs, const int32_t *lev, const double *x, const double *y,
+                         int32_t *nuniq_out);
+int rf_obs_plan(const rf_grid *g, int32_t nobs, const int32_t *lev, const double *x, const double *y, void *plan,
+                size_t plan_bytes);
+int rf_obs_apply(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t npts, rf_prec prec, const void *field,
+                 void *obs, void *stream);
+int rf_obs_adjoint(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t npts, rf_prec prec, const void *obs,
+                   void *field, void *stream);
+
 /* Static description of a status code. */
 const char *rf_strerror(int status);
 

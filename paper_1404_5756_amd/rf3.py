@@ -71,6 +71,16 @@ def lib() -> ctypes.CDLL:
         L.rf3_batch_plan.argtypes = [B, I, P, S]
         L.rf3_apply_batch.restype = I
         L.rf3_apply_batch.argtypes = [B, I, I, I, P, S, P]
+        D = ctypes.POINTER(ctypes.c_double)
+        IP = ctypes.POINTER(ctypes.c_int32)
+        L.rf_obs_plan_bytes.restype = S
+        L.rf_obs_plan_bytes.argtypes = [G, I, IP, D, D, IP]
+        L.rf_obs_plan.restype = I
+        L.rf_obs_plan.argtypes = [G, I, IP, D, D, P, S]
+        for name in ("rf_obs_apply", "rf_obs_adjoint"):
+            f = getattr(L, name)
+            f.restype = I
+            f.argtypes = [P, I, I, ctypes.c_int64, I, P, P, P]
         L.rf_strerror.restype = ctypes.c_char_p
         L.rf_strerror.argtypes = [I]
         _lib = L
@@ -166,3 +176,34 @@ def rf3_apply_batch(items, prec, adjoint, plan_dev, plan_bytes, stream=None):
     arr, _keep = _items(items)
     _check(lib().rf3_apply_batch(arr, len(items), int(prec), int(adjoint), _ptr(plan_dev), int(plan_bytes),
                                  _stream(stream)), "rf3_apply_batch")
+
+
+def rf_obs_plan(g, lev, x, y):
+    """Host gather tables of the bilinear observation operator: (plan bytes, nuniq)."""
+    import numpy as np
+    lev = np.ascontiguousarray(lev, dtype=np.int32)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    n = len(lev)
+    if len(x) != n or len(y) != n:
+        raise ValueError("lev, x, y must have the same length")
+    IP = ctypes.POINTER(ctypes.c_int32)
+    D = ctypes.POINTER(ctypes.c_double)
+    nu = ctypes.c_int32(0)
+    args = (ctypes.byref(g), n, lev.ctypes.data_as(IP), x.ctypes.data_as(D), y.ctypes.data_as(D))
+    nb = lib().rf_obs_plan_bytes(*args, ctypes.byref(nu))
+    if nb == 0:
+        raise RFError(RF_E_ARG, "rf_obs_plan_bytes")
+    buf = ctypes.create_string_buffer(nb)
+    _check(lib().rf_obs_plan(*args, buf, nb), "rf_obs_plan")
+    return buf.raw, nu.value
+
+
+def rf_obs_apply(plan_dev, nobs, nuniq, npts, prec, field, obs, stream=None):
+    _check(lib().rf_obs_apply(_ptr(plan_dev), int(nobs), int(nuniq), int(npts), int(prec), _ptr(field), _ptr(obs),
+                              _stream(stream)), "rf_obs_apply")
+
+
+def rf_obs_adjoint(plan_dev, nobs, nuniq, npts, prec, obs, field, stream=None):
+    _check(lib().rf_obs_adjoint(_ptr(plan_dev), int(nobs), int(nuniq), int(npts), int(prec), _ptr(obs), _ptr(field),
+                                _stream(stream)), "rf_obs_adjoint")

@@ -1,0 +1,135 @@
+"""3D-VAR harness on the GPU: the covariance operator as a differentiable torch
+operation, the bilinear observation operator, the cost and its gradient, and a
+conjugate-gradient minimiser.
+
+Sec. 2 writes the analysis as the minimum of
+    J(v) = 1/2 v.v + 1/2 (H V v - y).R^-1.(H V v - y),   grad J = v + V^T H^T R^-1 (H V v - y),
+with the background error covariance factored as B = V V^T and V = V_H (here
+G_y G_x per level).  The minimiser calls V and V^T once per iteration; both,
+and H, H^T, are librf3 calls.  torch only holds the vectors and does the
+dot products and vector updates of CG.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import rf3
+from .operator import HorizontalCovariance
+
+
+class RF3XY(torch.autograd.Function):
+    """y = V x with V = G_y G_x; the backward pass applies V^T (no saved activations)."""
+
+    @staticmethod
+    def forward(ctx, x, op):
+        ctx.op = op
+        return op.apply(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.op.adjoint(g.contiguous()), None
+
+
+def rf3xy(x: torch.Tensor, op: HorizontalCovariance) -> torch.Tensor:
+    return RF3XY.apply(x, op)
+
+
+class Observations:
+    """Bilinear observation operator on one [nlev][ny][nx] field (rf_obs_*)."""
+
+    def __init__(self, op: HorizontalCovariance, lev, x, y, device=None):
+        self.op = op
+        plan, self.nuniq = rf3.rf_obs_plan(op.grid, lev, x, y)
+        self.nobs = len(lev)
+        self.npts = op.nx * op.ny * op.nlev
+        dev = op.device if device is None else device
+        # torch's caching allocator returns 512-byte aligned blocks
+        self.plan = torch.frombuffer(bytearray(plan), dtype=torch.uint8).to(dev)
+        self.shape = (op.nlev, op.ny, op.nx)
+
+    @staticmethod
+    def _prec(t):
+        if t.dtype == torch.float32:
+            return rf3.RF_FP32
+        if t.dtype == torch.float64:
+            return rf3.RF_FP64
+        raise TypeError(f"float32 or float64 expected, got {t.dtype}")
+
+    def apply(self, field, out=None, stream=None):
+        field = field.contiguous()
+        if field.numel() != self.npts:
+            raise ValueError(f"field has {field.numel()} points, the plan {self.npts}")
+        out = torch.empty(self.nobs, dtype=field.dtype, device=field.device) if out is None else out
+        rf3.rf_obs_apply(self.plan, self.nobs, self.nuniq, self.npts, self._prec(field), field, out, stream)
+        return out
+
+    def adjoint(self, obs, out=None, stream=None):
+        obs = obs.contiguous()
+        if obs.numel() != self.nobs:
+            raise ValueError(f"{obs.numel()} values for {self.nobs} observations")
+        out = torch.empty(self.shape, dtype=obs.dtype, device=obs.device) if out is None else out
+        rf3.rf_obs_adjoint(self.plan, self.nobs, self.nuniq, self.npts, self._prec(obs), obs, out, stream)
+        return out
+
+
+def _dot(a, b):
+    """Dot product accumulated in FP64."""
+    return float((a * b).sum(dtype=torch.float64))
+
+
+class Var3D:
+    """J(v), grad J(v) and CG for the control variable v (shape [nlev][ny][nx])."""
+
+    def __init__(self, op: HorizontalCovariance, obs: Observations, yobs, rinv):
+        self.op, self.obs = op, obs
+        self.y = yobs
+        self.rinv = rinv   # scalar or tensor over the observations
+
+    def cost_grad(self, v):
+        d = self.obs.apply(self.op.apply(v)) - self.y
+        rd = self.rinv * d
+        J = 0.5 * _dot(v, v) + 0.5 * _dot(d, rd)
+        g = v + self.op.adjoint(self.obs.adjoint(rd))
+        return J, g
+
+    def hess(self, p):
+        """(I + V^T H^T R^-1 H V) p."""
+        return p + self.op.adjoint(self.obs.adjoint(self.rinv * self.obs.apply(self.op.apply(p))))
+
+    def cg(self, iters, callback=None):
+        """CG from v = 0 on the normal equations; returns v and J after every iteration."""
+        v = torch.zeros(self.obs.shape, dtype=self.y.dtype, device=self.y.device)
+        r = self.op.adjoint(self.obs.adjoint(self.rinv * self.y))
+        p = r.clone()
+        rr = _dot(r, r)
+        costs = [self.cost_grad(v)[0]]
+        for k in range(iters):
+            q = self.hess(p)
+            pq = _dot(p, q)
+            if pq <= 0.0 or rr == 0.0:
+                break
+            a = rr / pq
+            v.add_(p, alpha=a)
+            r.sub_(q, alpha=a)
+            rr_new = _dot(r, r)
+            p.mul_(rr_new / rr).add_(r)
+            rr = rr_new
+            costs.append(self.cost_grad(v)[0])
+            if callback is not None:
+                callback(k, v)
+        return v, costs
+
+
+def synthetic_problem(w, nobs, device, dtype=torch.float32, op=None, obs_noise=0.5, seed=None):
+    """C5-style twin experiment on workload w: v_true ~ N(0,1) on sea, y = H V v_true + noise."""
+    from . import synth
+    op = op or HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode,
+                                    device=device)
+    lev, xs, ys = synth.c5_observations(w, nobs, seed=seed)
+    obs = Observations(op, lev, xs, ys)
+    rng = np.random.default_rng(synth.SEEDS["c5"] if seed is None else seed)
+    vt = rng.standard_normal((w.nlev, w.ny, w.nx)) * (w.mask[0] != 0)
+    vt = torch.from_numpy(vt).to(device=device, dtype=dtype)
+    yobs = obs.apply(op.apply(vt)) + obs_noise * torch.from_numpy(rng.standard_normal(nobs)).to(device, dtype)
+    return Var3D(op, obs, yobs, 1.0 / obs_noise ** 2), vt

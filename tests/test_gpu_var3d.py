@@ -1,0 +1,118 @@
+"""3D-VAR harness on the GPU against the FP64 reference (oracle/var3d.py).
+
+Observation operator and its adjoint, the autograd function (backward = V^T,
+torch.autograd.gradcheck in FP64), the cost gradient against central
+differences (FP64) and against the FP64 gradient (FP32), and CG: monotone J
+and the same iterates as the reference CG.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import var3d as ov
+from paper_1404_5756_amd import synth
+from paper_1404_5756_amd.operator import HorizontalCovariance
+from paper_1404_5756_amd.var3d import Observations, Var3D, rf3xy, synthetic_problem
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def grid():
+    w = synth.random_case(31, 64, 96, 3, 0.3, 4, (1.5, 8.0), 3.0, "fit", False, False)
+    op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode, device=DEV)
+    lev, xs, ys = synth.c5_observations(w, 1500, seed=11)
+    return w, op, lev, xs, ys
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_obs_operator_matches_reference(grid, dtype):
+    w, op, lev, xs, ys = grid
+    obs = Observations(op, lev, xs, ys)
+    idx, wt = ov.obs_weights(w.nx, w.ny, lev, xs, ys)
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((w.nlev, w.ny, w.nx))
+    d = rng.standard_normal(len(lev))
+    got = obs.apply(torch.from_numpy(f).to(DEV, dtype)).double().cpu().numpy()
+    tol = 1e-13 if dtype == torch.float64 else 1e-6
+    assert rel(got, ov.obs_apply(f, idx, wt)) < tol
+    gt = obs.adjoint(torch.from_numpy(d).to(DEV, dtype)).double().cpu().numpy().ravel()
+    assert rel(gt, ov.obs_adjoint(d, idx, wt, f.size)) < tol
+
+
+def test_obs_adjoint_is_deterministic(grid):
+    w, op, lev, xs, ys = grid
+    obs = Observations(op, lev, xs, ys)
+    d = torch.randn(len(lev), device=DEV)
+    a = obs.adjoint(d)
+    for _ in range(3):
+        assert torch.equal(obs.adjoint(d), a)
+
+
+def test_autograd_backward_is_the_adjoint(grid, orc):
+    w, op, *_ = grid
+    x = torch.randn(w.nlev, w.ny, w.nx, device=DEV, requires_grad=True)
+    g = torch.randn(w.nlev, w.ny, w.nx, device=DEV)
+    (rf3xy(x, op) * g).sum().backward()
+    assert torch.equal(x.grad, op.adjoint(g))
+    P = orc.Problem(w.mask, w.sigma_x, w.sigma_y, n_img=w.n_img, qmode=orc.QMODES[w.qmode])
+    assert rel(x.grad.double().cpu().numpy(), P.rf3_adjoint(g.double().cpu().numpy()[None])[0]) < 1e-5
+
+
+def test_gradcheck_fp64():
+    w = synth.random_case(32, 8, 10, 1, 0.2, 2, (1.5, 4.0), 3.0, "fit", False, False)
+    op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, 1, n_img=w.n_img, qmode=w.qmode, device=DEV)
+    x = torch.randn(1, 8, 10, device=DEV, dtype=torch.float64, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda t: rf3xy(t, op), (x,), eps=1e-6, atol=1e-9, rtol=1e-7)
+
+
+@pytest.fixture(scope="module")
+def problems(grid):
+    w, op, *_ = grid
+    p64, vt = synthetic_problem(w, 1500, DEV, torch.float64, op=op, seed=11)
+    p32 = Var3D(op, p64.obs, p64.y.float(), p64.rinv)
+    return w, p64, p32
+
+
+def test_gradient_central_differences_fp64(problems):
+    w, p64, _ = problems
+    gen = torch.Generator(device=DEV).manual_seed(5)
+    v = torch.randn(p64.obs.shape, generator=gen, device=DEV, dtype=torch.float64)
+    d = torch.randn(p64.obs.shape, generator=gen, device=DEV, dtype=torch.float64)
+    J, g = p64.cost_grad(v)
+    eps = 1e-2 * float(v.norm() / d.norm())
+    fd = (p64.cost_grad(v + eps * d)[0] - p64.cost_grad(v - eps * d)[0]) / (2 * eps)
+    gd = float((g * d).sum())
+    assert abs(fd - gd) <= 1e-6 * abs(gd)
+
+
+def test_fp32_gradient_matches_fp64(problems):
+    w, p64, p32 = problems
+    gen = torch.Generator(device=DEV).manual_seed(6)
+    v = torch.randn(p64.obs.shape, generator=gen, device=DEV, dtype=torch.float64)
+    _, g64 = p64.cost_grad(v)
+    _, g32 = p32.cost_grad(v.float())
+    assert rel(g32.double().cpu().numpy(), g64.cpu().numpy()) < 1e-5
+
+
+def test_cg_monotone_and_matches_reference(problems, orc, grid):
+    w, p64, p32 = problems
+    _, op, lev, xs, ys = grid
+    iters = 12
+    v64, c64 = p64.cg(iters)
+    assert all(c1 <= c0 * (1 + 1e-12) for c0, c1 in zip(c64, c64[1:]))
+    v32, c32 = p32.cg(iters)
+    assert all(c1 <= c0 * (1 + 1e-6) for c0, c1 in zip(c32, c32[1:]))
+    # reference CG: oracle V, V^T and H
+    P = orc.Problem(w.mask, w.sigma_x, w.sigma_y, n_img=w.n_img, qmode=orc.QMODES[w.qmode])
+    shape = (1, w.nlev, w.ny, w.nx)
+    idx, wt = ov.obs_weights(w.nx, w.ny, lev, xs, ys)
+    its = ov.cg(lambda v: P.rf3(v.reshape(shape)).ravel(), lambda v: P.rf3_adjoint(v.reshape(shape)).ravel(),
+                idx, wt, p64.y.cpu().numpy(), p64.rinv, int(np.prod(shape)), iters)
+    assert rel(v64.cpu().numpy().ravel(), its[-1]) < 1e-8
+    assert rel(v32.double().cpu().numpy().ravel(), its[-1]) < 1e-4

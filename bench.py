@@ -26,12 +26,81 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpoints/s of 3rd-RF fwd+adjoint (FP32 batched vs FP64 1st-RF) and % HBM peak"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1404_5756_amd", "csrc", "sweep_fast.hip")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def bench_batch(torch, dev, args):
+    """64 uneven grids (C4) in one batch: forward + adjoint, against one call per grid."""
+    from paper_1404_5756_amd import synth
+    from paper_1404_5756_amd.operator import Batch, HorizontalCovariance
+    ws = synth.c4_batch()
+    gen = torch.Generator(device=dev).manual_seed(synth.SEEDS["c4"])
+    t0 = time.time()
+    ops, xs = [], []
+    for w in ws:
+        ops.append(HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode,
+                                        device=dev))
+        xs.append(torch.randn((1, w.nlev, w.ny, w.nx), generator=gen, device=dev))
+    b = Batch([(op, x, x) for op, x in zip(ops, xs)])   # in place
+    torch.cuda.synchronize()
+    setup = time.time() - t0
+    pts = b.points
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(3, args.steps // 4)
+    ms_b = timed(lambda: (b.apply(False), b.apply(True)), reps)
+    ms_i = timed(lambda: [(op.apply(x, out=x), op.adjoint(x, out=x)) for op, x in zip(ops, xs)], reps)
+    log(f"batch C4: {len(ws)} grids, {pts / 1e9:.3f} G points: batched fwd+adj {ms_b:.2f} ms, "
+        f"per-grid calls {ms_i:.2f} ms (setup {setup:.1f} s)")
+    res = {"grids": len(ws), "points": pts, "ms_fwd_adj": round(ms_b, 3),
+           "gpoints_s": round(pts / (ms_b * 1e-3) / 1e9, 2), "ms_per_grid_calls": round(ms_i, 3),
+           "speedup_vs_per_grid_calls": round(ms_i / ms_b, 3), "setup_s": round(setup, 1)}
+    del b, ops, xs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_cg(torch, dev, w, op, args):
+    """3D-VAR CG iterations (C5) on the C3 grid with 200k bilinear observations, FP32."""
+    from paper_1404_5756_amd.var3d import synthetic_problem
+    t0 = time.time()
+    prob, _vt = synthetic_problem(w, 200_000, dev, torch.float32, op=op)
+    torch.cuda.synchronize()
+    setup = time.time() - t0
+    prob.cg(1, track_cost=False)   # warm up
+    torch.cuda.synchronize()
+    # iterations alone (V, H, H^T, V^T and the CG vector updates; J is evaluated only at both ends)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    _v, ends = prob.cg(args.cg_iters, track_cost=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    # a second run with J after every iteration checks that J never increases
+    _v2, costs = prob.cg(args.cg_iters)
+    log(f"CG C5: {args.cg_iters} iterations in {ms_total:.1f} ms (incl. J at both ends); "
+        f"J {costs[0]:.4e} -> {costs[-1]:.4e}")
+    return {"iterations": args.cg_iters, "ms_per_iteration": round(ms_total / args.cg_iters, 3),
+            "obs": 200_000, "J_first": costs[0], "J_last": costs[-1],
+            "J_monotone": bool(all(c1 <= c0 * (1 + 1e-6) for c0, c1 in zip(costs, costs[1:]))),
+            "setup_s": round(setup, 1)}
 
 
 def main():
@@ -44,6 +113,9 @@ def main():
                     help="levels of the workload the CPU oracle runs on (0 = all levels)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-rf1", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-grid batch (C4)")
+    ap.add_argument("--no-cg", action="store_true", help="skip the 3D-VAR CG iterations (C5)")
+    ap.add_argument("--cg-iters", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); every (field, level) is an "
@@ -107,7 +179,8 @@ def main():
     achieved = bytes_per_launch / (kern[dom] * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
-        tf = json.load(open(TRAFFIC_FILE))
+        # '#' lines are commentary; the rest is one JSON object written from rocprofv3 counters
+        tf = json.loads("".join(l for l in open(TRAFFIC_FILE) if not l.lstrip().startswith("#")))
         src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
         if tf.get("kernel_src_sha256") == src_hash and dom in tf.get("bytes_per_launch", {}):
             traffic = tf["bytes_per_launch"][dom]
@@ -140,6 +213,14 @@ def main():
                "speedup_rf3_fp32_fwd_vs_rf1_fp64_k5": round(ms_rf1 / ms_fwd, 2)}
         log(f"1st-RF FP64 K=5: {ms_rf1:.3f} ms; 3rd-RF FP32 forward {ms_fwd:.3f} ms")
         del x64, o64
+
+    # ---- a plain copy of the field (known bytes): the reference that scales the
+    # FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 run of this script
+    out_f.copy_(x)
+    torch.cuda.synchronize()
+
+    batch = None if args.no_batch else bench_batch(torch, dev, args)
+    cg = None if args.no_cg else bench_cg(torch, dev, w, op, args)
 
     # ---- CPU oracle baseline on a sample of levels, and parity on that sample
     cpu = None
@@ -183,6 +264,8 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "rf3_fwd_ms": round(ms_fwd, 4),
         "rf1_fp64_k5": rf1,
+        "batch_c4": batch,
+        "cg_c5": cg,
         "parity_sample": parity,
         "setup_s": round(setup_s, 2),
     }

@@ -97,8 +97,9 @@ class Var3D:
         """(I + V^T H^T R^-1 H V) p."""
         return p + self.op.adjoint(self.obs.adjoint(self.rinv * self.obs.apply(self.op.apply(p))))
 
-    def cg(self, iters, callback=None):
-        """CG from v = 0 on the normal equations; returns v and J after every iteration."""
+    def cg(self, iters, callback=None, track_cost=True):
+        """CG from v = 0 on the normal equations; returns v and J after every iteration
+        (only J at v = 0 and at the end when track_cost is False)."""
         v = torch.zeros(self.obs.shape, dtype=self.y.dtype, device=self.y.device)
         r = self.op.adjoint(self.obs.adjoint(self.rinv * self.y))
         p = r.clone()
@@ -115,9 +116,12 @@ class Var3D:
             rr_new = _dot(r, r)
             p.mul_(rr_new / rr).add_(r)
             rr = rr_new
-            costs.append(self.cost_grad(v)[0])
+            if track_cost:
+                costs.append(self.cost_grad(v)[0])
             if callback is not None:
                 callback(k, v)
+        if not track_cost:
+            costs.append(self.cost_grad(v)[0])
         return v, costs
 
 

@@ -1,10 +1,10 @@
 """FP64 reference of the 3D-VAR harness pieces (TEST INFRASTRUCTURE ONLY).
 
-Used by ``tests/`` only.  Written from the cost function of Sec. 2 (eqs. for J
-and its gradient with the control-variable transform x = V v): the bilinear
-observation operator H, its transpose, the cost J(v) = v.v/2 +
-(HVv - y).R^-1.(HVv - y)/2 and its gradient v + V^T H^T R^-1 (HVv - y), and a
-textbook conjugate-gradient solve of the normal equations
+Used by ``tests/`` only.  Written from Sec. 2.1 (the quadratic cost in the
+increment, eq. "functional2", and its preconditioned system, eq. "eight", with
+B = V V^T), in the control variable v (increment = V v): the bilinear observation
+operator H, its transpose, the cost J(v) = v.v/2 + (HVv - y).R^-1.(HVv - y)/2 and its
+gradient v + V^T H^T R^-1 (HVv - y), and a textbook conjugate-gradient solve of
 (I + V^T H^T R^-1 H V) v = V^T H^T R^-1 y.  Plain loops and numpy only.
 """
 from __future__ import annotations

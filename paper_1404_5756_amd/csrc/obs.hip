@@ -1,6 +1,6 @@
 // Bilinear observation operator H and its adjoint H^T for the 3D-VAR harness
-// (the minimiser of Sec. 2 applies V and V^T, then H and H^T, every
-// iteration).  Observation o sits at level lev[o] and position (x[o], y[o]) in
+// (the conjugate-gradient minimiser of Sec. 2.1 applies H^T R^-1 H and the
+// covariance factors every iteration).  Observation o sits at level lev[o] and position (x[o], y[o]) in
 // grid units; it reads the four surrounding grid points with bilinear weights.
 //
 // H is a gather (one thread per observation).  H^T is a gather too, over the

@@ -2,12 +2,14 @@
 operation, the bilinear observation operator, the cost and its gradient, and a
 conjugate-gradient minimiser.
 
-Sec. 2 writes the analysis as the minimum of
-    J(v) = 1/2 v.v + 1/2 (H V v - y).R^-1.(H V v - y),   grad J = v + V^T H^T R^-1 (H V v - y),
-with the background error covariance factored as B = V V^T and V = V_H (here
-G_y G_x per level).  The minimiser calls V and V^T once per iteration; both,
-and H, H^T, are librf3 calls.  torch only holds the vectors and does the
-dot products and vector updates of CG.
+Sec. 2.1 minimises a quadratic cost in the increment through a preconditioned
+linear system solved by conjugate gradients, with the background covariance
+factored as B = V V^T.  With the control variable v (increment = V v) the cost is
+    J(v) = 1/2 v.v + 1/2 (H V v - y).R^-1.(H V v - y),   grad J = v + V^T H^T R^-1 (H V v - y)
+and CG solves (I + V^T H^T R^-1 H V) v = V^T H^T R^-1 y, the same minimiser.
+Here V = V_H = G_y G_x per level.  Every iteration calls V and V^T once; both,
+and H, H^T, are librf3 calls.  torch only holds the vectors and does the dot
+products and vector updates of CG.
 """
 from __future__ import annotations
 

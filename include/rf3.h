@@ -194,6 +194,30 @@ int rf_obs_apply(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t npts
 int rf_obs_adjoint(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t npts, rf_prec prec, const void *obs,
                    void *field, void *stream);
 
+/* 3D-VAR harness: vector steps of conjugate gradients (Sec. 2.1 solves its
+ * preconditioned system by CG).  The iteration's scalars live in device
+ * memory `s` (double[RF_CG_SLOTS], caller-owned), so an iteration is a chain
+ * of launches without host round trips.  Dot products accumulate in FP64 and
+ * are deterministic: a fixed grid of blocks writes partial sums into `work`
+ * (caller-owned, device, rf_cg_work_bytes() bytes), then one block adds them
+ * in a fixed order.  Vectors are n elements of `prec`, device memory.
+ *   rf_dot:      s[slot] = a.b
+ *   rf_cg_q_dot: q = p + w;  s[RF_CG_PQ] = p.q
+ *   rf_cg_step:  a = s[RF_CG_RR] / s[RF_CG_PQ] (0 if s[RF_CG_PQ] <= 0);
+ *                v += a p;  r -= a q;  s[RF_CG_RR_NEW] = r.r
+ *   rf_cg_dir:   p = r + (s[RF_CG_RR_NEW] / s[RF_CG_RR]) p;  s[RF_CG_RR] = s[RF_CG_RR_NEW]
+ * Asynchronous on `stream`; no allocation.  RF_E_ARG on null pointers,
+ * n < 1, a bad precision or slot. */
+enum { RF_CG_RR = 0, RF_CG_PQ = 1, RF_CG_RR_NEW = 2, RF_CG_SLOTS = 8 };
+size_t rf_cg_work_bytes(void);
+int rf_dot(rf_prec prec, int64_t n, const void *a, const void *b, void *work, double *s, int32_t slot,
+           void *stream);
+int rf_cg_q_dot(rf_prec prec, int64_t n, const void *p, const void *w, void *q, void *work, double *s,
+                void *stream);
+int rf_cg_step(rf_prec prec, int64_t n, const void *p, const void *q, void *v, void *r, void *work, double *s,
+               void *stream);
+int rf_cg_dir(rf_prec prec, int64_t n, const void *r, void *p, double *s, void *stream);
+
 /* Static description of a status code. */
 const char *rf_strerror(int status);
 

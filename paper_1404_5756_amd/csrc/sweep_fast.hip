@@ -524,20 +524,10 @@ __device__ __forceinline__ void y_block(const float *in, float *out, const float
                 roff = fresh_int(min(roff + rowb, last));
             }
         }
-        {   // input only at sea points
-            const uint64_t *sp = lm + 2 * lys + r0;
-#pragma unroll
-            for (int b = 0; b < LB; ++b) {
-                const u32x16 m = sload16(sp + 8 * b);
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (8 * b + q < L)
-#pragma unroll
-                        for (int p = 0; p < P; ++p) v[p][8 * b + q] = zero_if(v[p][8 * b + q], m64_of(m, q));
-            }
-        }
-        // one pass over the chunk for all P planes.  MODE 1: local (no output),
-        // MODE 2: output into v (descending also applies the sea mask).
+        // one pass over the chunk for all P planes.  MODE 1: local (no output; the
+        // first pass also masks the input to sea points as the rows arrive),
+        // MODE 2: output into v; the last pass (descending) applies the output sea
+        // mask and stores each row as it is produced.
         auto pass = [&](St *x, auto DC, auto MC) {
             constexpr bool desc = decltype(DC)::value;
             constexpr int mode = decltype(MC)::value;
@@ -554,6 +544,9 @@ __device__ __forceinline__ void y_block(const float *in, float *out, const float
                 cur = fresh_int(cur + (desc ? -crow : crow));
                 return z;
             };
+            constexpr bool first = !desc && mode == 1, last = desc && mode == 2;
+            const int lim = ny * rowb;
+            int soff = fresh_int((r0 + L - 1) * rowb);   // store offset of the current row (last pass)
             u32x4 win[kYWin];
 #pragma unroll
             for (int q = 0; q < kYWin; ++q) win[q] = cload();
@@ -562,7 +555,7 @@ __device__ __forceinline__ void y_block(const float *in, float *out, const float
                 const int b = desc ? LB - 1 - bb : bb;
                 const u32x16 m = sload16(rp + 8 * b);
                 u32x16 sm;
-                if (mode == 2 && desc) sm = sload16(sp + 8 * b);
+                if (first || last) sm = sload16(sp + 8 * b);
 #pragma unroll
                 for (int qq = 0; qq < 8; ++qq) {
                     const int q = desc ? 7 - qq : qq;
@@ -576,6 +569,7 @@ __device__ __forceinline__ void y_block(const float *in, float *out, const float
                     const uint64_t mm = m64_of(m, q);
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
+                        if (first) v[p][i] = zero_if(v[p][i], m64_of(sm, q));   // input only at sea points
                         float o;
                         if (!ADJ) {
                             st_reset(x[p], mm);
@@ -586,6 +580,14 @@ __device__ __forceinline__ void y_block(const float *in, float *out, const float
                             st_reset(x[p], mm);
                         }
                         if (mode == 2) v[p][i] = desc ? zero_if(o, m64_of(sm, q)) : o;
+                    }
+                    if (last) {
+                        if (soff < lim) {   // rows past the grid are not stored
+#pragma unroll
+                            for (int p = 0; p < P; ++p)
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[p][i]), ro[p], cb, soff, 0);
+                        }
+                        soff = fresh_int(soff - rowb);
                     }
                     mem_fence_compiler();   // keep the window's loads from being hoisted further
                 }
@@ -625,19 +627,6 @@ __device__ __forceinline__ void y_block(const float *in, float *out, const float
         };
         sweep(std::false_type{});
         sweep(std::true_type{});
-        {
-            const int lim = ny * rowb;
-            int roff = fresh_int(r0 * rowb);
-#pragma unroll
-            for (int i = 0; i < L; ++i) {
-                if (roff < lim) {   // rows past the grid are not stored
-#pragma unroll
-                    for (int p = 0; p < P; ++p)
-                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[p][i]), ro[p], cb, roff, 0);
-                }
-                roff = fresh_int(roff + rowb);
-            }
-        }
         __syncthreads();   // bsh is rewritten by the next plane group
     }
 }

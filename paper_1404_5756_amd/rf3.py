@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librf3.so")
 RF_OK, RF_E_ARG, RF_E_SHAPE, RF_E_SIGMA, RF_E_HIP, RF_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 RF_FP32, RF_FP64 = 0, 1
 RF_Q_LITERAL, RF_Q_VARMATCH, RF_Q_FIT = 0, 1, 2
+RF_CG_RR, RF_CG_PQ, RF_CG_RR_NEW, RF_CG_SLOTS = 0, 1, 2, 8
 QMODES = {"literal": RF_Q_LITERAL, "varmatch": RF_Q_VARMATCH, "fit": RF_Q_FIT}
 
 
@@ -81,6 +82,17 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.restype = I
             f.argtypes = [P, I, I, ctypes.c_int64, I, P, P, P]
+        L.rf_cg_work_bytes.restype = S
+        L.rf_cg_work_bytes.argtypes = []
+        L64 = ctypes.c_int64
+        L.rf_dot.restype = I
+        L.rf_dot.argtypes = [I, L64, P, P, P, P, I, P]
+        L.rf_cg_q_dot.restype = I
+        L.rf_cg_q_dot.argtypes = [I, L64, P, P, P, P, P, P]
+        L.rf_cg_step.restype = I
+        L.rf_cg_step.argtypes = [I, L64, P, P, P, P, P, P, P]
+        L.rf_cg_dir.restype = I
+        L.rf_cg_dir.argtypes = [I, L64, P, P, P, P]
         L.rf_strerror.restype = ctypes.c_char_p
         L.rf_strerror.argtypes = [I]
         _lib = L
@@ -207,3 +219,26 @@ def rf_obs_apply(plan_dev, nobs, nuniq, npts, prec, field, obs, stream=None):
 def rf_obs_adjoint(plan_dev, nobs, nuniq, npts, prec, obs, field, stream=None):
     _check(lib().rf_obs_adjoint(_ptr(plan_dev), int(nobs), int(nuniq), int(npts), int(prec), _ptr(obs), _ptr(field),
                                 _stream(stream)), "rf_obs_adjoint")
+
+
+def rf_cg_work_bytes() -> int:
+    return lib().rf_cg_work_bytes()
+
+
+def rf_dot(prec, n, a, b, work, s, slot, stream=None):
+    _check(lib().rf_dot(int(prec), int(n), _ptr(a), _ptr(b), _ptr(work), _ptr(s), int(slot), _stream(stream)),
+           "rf_dot")
+
+
+def rf_cg_q_dot(prec, n, p, w, q, work, s, stream=None):
+    _check(lib().rf_cg_q_dot(int(prec), int(n), _ptr(p), _ptr(w), _ptr(q), _ptr(work), _ptr(s), _stream(stream)),
+           "rf_cg_q_dot")
+
+
+def rf_cg_step(prec, n, p, q, v, r, work, s, stream=None):
+    _check(lib().rf_cg_step(int(prec), int(n), _ptr(p), _ptr(q), _ptr(v), _ptr(r), _ptr(work), _ptr(s),
+                            _stream(stream)), "rf_cg_step")
+
+
+def rf_cg_dir(prec, n, r, p, s, stream=None):
+    _check(lib().rf_cg_dir(int(prec), int(n), _ptr(r), _ptr(p), _ptr(s), _stream(stream)), "rf_cg_dir")

@@ -8,8 +8,8 @@ factored as B = V V^T.  With the control variable v (increment = V v) the cost i
     J(v) = 1/2 v.v + 1/2 (H V v - y).R^-1.(H V v - y),   grad J = v + V^T H^T R^-1 (H V v - y)
 and CG solves (I + V^T H^T R^-1 H V) v = V^T H^T R^-1 y, the same minimiser.
 Here V = V_H = G_y G_x per level.  Every iteration calls V and V^T once; both,
-and H, H^T, are librf3 calls.  torch only holds the vectors and does the dot
-products and vector updates of CG.
+H, H^T and the CG vector steps (deterministic FP64 dot products, scalars kept
+on the device) are librf3 calls.  torch only holds the vectors.
 """
 from __future__ import annotations
 
@@ -75,11 +75,6 @@ class Observations:
         return out
 
 
-def _dot(a, b):
-    """Dot product accumulated in FP64."""
-    return float((a * b).sum(dtype=torch.float64))
-
-
 class Var3D:
     """J(v), grad J(v) and CG for the control variable v (shape [nlev][ny][nx])."""
 
@@ -87,37 +82,49 @@ class Var3D:
         self.op, self.obs = op, obs
         self.y = yobs
         self.rinv = rinv   # scalar or tensor over the observations
+        dev = yobs.device
+        self.prec = Observations._prec(yobs)
+        self.s = torch.zeros(rf3.RF_CG_SLOTS, dtype=torch.float64, device=dev)   # device scalars
+        self.work = torch.empty(rf3.rf_cg_work_bytes() // 8, dtype=torch.float64, device=dev)
+
+    def _dots(self, pairs):
+        """FP64 dot products (deterministic, librf3), returned to the host."""
+        for k, (a, b) in enumerate(pairs):
+            rf3.rf_dot(self.prec, a.numel(), a, b, self.work, self.s, 3 + k)
+        return self.s[3:3 + len(pairs)].tolist()
 
     def cost_grad(self, v):
         d = self.obs.apply(self.op.apply(v)) - self.y
         rd = self.rinv * d
-        J = 0.5 * _dot(v, v) + 0.5 * _dot(d, rd)
+        vv, drd = self._dots([(v, v), (d, rd)])
+        J = 0.5 * vv + 0.5 * drd
         g = v + self.op.adjoint(self.obs.adjoint(rd))
         return J, g
 
+    def _vthv(self, p):
+        """V^T H^T R^-1 H V p."""
+        return self.op.adjoint(self.obs.adjoint(self.rinv * self.obs.apply(self.op.apply(p))))
+
     def hess(self, p):
         """(I + V^T H^T R^-1 H V) p."""
-        return p + self.op.adjoint(self.obs.adjoint(self.rinv * self.obs.apply(self.op.apply(p))))
+        return p + self._vthv(p)
 
     def cg(self, iters, callback=None, track_cost=True):
         """CG from v = 0 on the normal equations; returns v and J after every iteration
-        (only J at v = 0 and at the end when track_cost is False)."""
+        (only J at v = 0 and at the end when track_cost is False).  The iteration's
+        scalars stay on the device: no host round trip inside the loop unless J is tracked."""
+        n = self.obs.npts
         v = torch.zeros(self.obs.shape, dtype=self.y.dtype, device=self.y.device)
         r = self.op.adjoint(self.obs.adjoint(self.rinv * self.y))
         p = r.clone()
-        rr = _dot(r, r)
+        q = torch.empty_like(p)
+        rf3.rf_dot(self.prec, n, r, r, self.work, self.s, rf3.RF_CG_RR)
         costs = [self.cost_grad(v)[0]]
         for k in range(iters):
-            q = self.hess(p)
-            pq = _dot(p, q)
-            if pq <= 0.0 or rr == 0.0:
-                break
-            a = rr / pq
-            v.add_(p, alpha=a)
-            r.sub_(q, alpha=a)
-            rr_new = _dot(r, r)
-            p.mul_(rr_new / rr).add_(r)
-            rr = rr_new
+            w = self._vthv(p)
+            rf3.rf_cg_q_dot(self.prec, n, p, w, q, self.work, self.s)       # q = p + w, p.q
+            rf3.rf_cg_step(self.prec, n, p, q, v, r, self.work, self.s)     # v += a p, r -= a q, r.r
+            rf3.rf_cg_dir(self.prec, n, r, p, self.s)                       # p = r + b p
             if track_cost:
                 costs.append(self.cost_grad(v)[0])
             if callback is not None:

@@ -116,3 +116,39 @@ def test_cg_monotone_and_matches_reference(problems, orc, grid):
                 idx, wt, p64.y.cpu().numpy(), p64.rinv, int(np.prod(shape)), iters)
     assert rel(v64.cpu().numpy().ravel(), its[-1]) < 1e-8
     assert rel(v32.double().cpu().numpy().ravel(), its[-1]) < 1e-4
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_cg_vector_kernels(dtype):
+    from paper_1404_5756_amd import rf3
+    prec = rf3.RF_FP32 if dtype == torch.float32 else rf3.RF_FP64
+    gen = torch.Generator(device=DEV).manual_seed(9)
+    n = 1_000_003
+    p, w, v, r = (torch.randn(n, generator=gen, device=DEV, dtype=dtype) for _ in range(4))
+    s = torch.zeros(rf3.RF_CG_SLOTS, dtype=torch.float64, device=DEV)
+    work = torch.empty(rf3.rf_cg_work_bytes() // 8, dtype=torch.float64, device=DEV)
+    P, W, Vv, Rr = (t.double().cpu().numpy() for t in (p, w, v, r))
+    # dot: FP64 accumulation, same bits on every call
+    rf3.rf_dot(prec, n, r, r, work, s, rf3.RF_CG_RR)
+    rr = float(s[rf3.RF_CG_RR])
+    assert abs(rr - Rr @ Rr) <= 1e-12 * (Rr @ Rr)
+    for _ in range(3):
+        rf3.rf_dot(prec, n, r, r, work, s, 5)
+        assert float(s[5]) == rr
+    q = torch.empty_like(p)
+    rf3.rf_cg_q_dot(prec, n, p, w, q, work, s)
+    Q = P + W
+    assert rel(q.double().cpu().numpy(), Q) < (1e-7 if dtype == torch.float32 else 1e-15)
+    assert abs(float(s[rf3.RF_CG_PQ]) - P @ Q) <= 1e-6 * abs(P @ Q)
+    a = rr / float(s[rf3.RF_CG_PQ])
+    rf3.rf_cg_step(prec, n, p, q, v, r, work, s)
+    qq = q.double().cpu().numpy()
+    Vn, Rn = Vv + a * P, Rr - a * qq
+    tol = 1e-6 if dtype == torch.float32 else 1e-14
+    assert rel(v.double().cpu().numpy(), Vn) < tol and rel(r.double().cpu().numpy(), Rn) < tol
+    rn = r.double().cpu().numpy()
+    assert abs(float(s[rf3.RF_CG_RR_NEW]) - rn @ rn) <= 1e-12 * (rn @ rn)
+    b = float(s[rf3.RF_CG_RR_NEW]) / rr
+    rf3.rf_cg_dir(prec, n, r, p, s)
+    assert rel(p.double().cpu().numpy(), rn + b * P) < tol
+    assert float(s[rf3.RF_CG_RR]) == float(s[rf3.RF_CG_RR_NEW])

@@ -17,10 +17,10 @@ using namespace rf;
 namespace {
 
 constexpr uint32_t kPlanMagic = 0x50424652u;   // "RFBP"
-constexpr uint32_t kPlanVersion = 1;
-// plane groups per y work unit: the unit's setup (transfer matrices into LDS)
-// is shared by this many plane groups of its column block
-constexpr int kYGroupsPerUnit = 4;
+constexpr uint32_t kPlanVersion = 2;
+// planes per y work unit: the unit's setup (transfer matrices into LDS) is
+// shared by this many planes of its column block
+constexpr int kYPlanesPerUnit = 8;
 
 struct PlanHeader {
     uint32_t magic, version;
@@ -104,14 +104,13 @@ int build(const rf_batch_item *items, int32_t n, HostPlan &P)
             for (int k = 0; k < groups; ++k) c.push_back(BatchUnit{i, r, k, groups});
             xl.push_back(std::move(c));
         }
-        // y: one cluster per column block, units of kYGroupsPerUnit plane groups
-        const int npg = (int)((nplanes + y_planes_per_lane(h.ly) - 1) / y_planes_per_lane(h.ly));
+        // y: one cluster per column block, units of kYPlanesPerUnit planes [b, c)
         const int nblk = (g->nx + kYCols - 1) / kYCols;
         auto &yl = yc[h.ly];
         for (int b = 0; b < nblk; ++b) {
             std::vector<BatchUnit> c;
-            for (int g0 = 0; g0 < npg; g0 += kYGroupsPerUnit)
-                c.push_back(BatchUnit{i, b, g0, std::min(npg, g0 + kYGroupsPerUnit)});
+            for (int p0 = 0; p0 < nplanes; p0 += kYPlanesPerUnit)
+                c.push_back(BatchUnit{i, b, p0, (int)std::min<long>(nplanes, p0 + kYPlanesPerUnit)});
             yl.push_back(std::move(c));
         }
     }

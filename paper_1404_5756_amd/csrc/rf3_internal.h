@@ -84,8 +84,8 @@ __host__ __device__ constexpr int y_planes_per_lane(int ly) { return ly <= 45 ? 
 
 // Batched FP32 application (batch.hip builds these on the host).  One entry per
 // item with its buffers and the tables of both directions; one unit per
-// workgroup: x {item, row, group, groups}, y {item, column block, first plane
-// group, end plane group}; item < 0 marks an idle unit.
+// workgroup: x {item, row, group, groups}, y {item, column block, first plane,
+// end plane}; item < 0 marks an idle unit.
 struct BatchEntry {
     const float *in;
     float *out;

@@ -470,47 +470,34 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x_batch(
 // ======================================================================
 constexpr int kYWin = 3;
 
-// One column block: plane groups g0, g0 + gstep, ... below g1 (group g = planes
-// P*g .. P*g + P-1).  phi: [2][16][64 * 9], bsh: [2][16][P][64 * 3] in LDS.
+// One unit: planes pl0 .. pl0 + P-1 of one column block, each lane one column
+// of each plane.  phi: [2][16][64 * 9] in LDS (filled by y_planes); bsh: LDS
+// array of [2][16][2][64 * 3] floats, used here as [2][16][P][64 * 3].
 template <int L, bool ADJ, int P>
-__device__ __forceinline__ void y_block(const float *in, float *out, const float4 *T, const uint64_t *LM,
-                                        const float *PHI, int nx_, int ny_, int nplanes, int blk, int g0,
-                                        int gstep, int g1, float (*phi)[kYWaves][kYCols * 9],
-                                        float (*bsh)[kYWaves][P][kYCols * 3])
+__device__ __forceinline__ void y_unit(const float *in, float *out, const float4 *T, const uint64_t *LM, int nx_,
+                                       int ny_, int blk, int pl0, float (*phi)[kYWaves][kYCols * 9], float *bsh_raw)
 {
+    auto bsh = reinterpret_cast<float (*)[kYWaves][P][kYCols * 3]>(bsh_raw);
     constexpr int LB = (L + 7) / 8;   // 8-row mask blocks per chunk
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = blk * kYCols + lane;
     const long plane = (long)nx_ * ny_;
     const int lys = lmy_stride(L);
     const uint64_t *lm = LM + (long)blk * 3 * lys + 8;   // entry r = row r
-    {
-        const int k0 = ADJ ? 2 : 0;
-        for (int e = threadIdx.x; e < 2 * kYWaves * kYCols; e += 64 * kYWaves) {
-            const int sw = e / (kYWaves * kYCols), rest = e % (kYWaves * kYCols);
-            const float *src = PHI + (((long)blk * 4 + k0 + sw) * kYWaves * kYCols + rest) * 12;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) phi[sw][rest / kYCols][(rest % kYCols) * 9 + q] = src[q];
-        }
-    }
     // columns past the grid: offsets beyond every buffer (loads read 0, stores are dropped)
     const uint32_t cb = col < nx_ ? (uint32_t)col * 4u : 0x7fffffffu;
     const uint32_t cbt = col < nx_ ? (uint32_t)col * 16u : 0x7fffffffu;
     const Rsrc rt = make_rsrc(T, (uint32_t)(plane * 16));
-    const int rowb_ = nx_ * 4;
-    __syncthreads();
-
-    for (int pg = g0 * P; pg < g1 * P && pg < nplanes; pg += gstep * P) {
-        // opaque per iteration: keeps the per-row offsets and conditions out of the
-        // loop preheader (hoisted, they would be live in SGPRs across the loop)
-        const int r0 = fresh_int(w * L), ny = fresh_int(ny_), rowb = fresh_int(rowb_), nx = fresh_int(nx_);
+    {
+        // opaque per unit: keeps the per-row offsets and conditions out of the
+        // enclosing loop's preheader (hoisted, they would be live in SGPRs across it)
+        const int r0 = fresh_int(w * L), ny = fresh_int(ny_), rowb = fresh_int(nx_ * 4), nx = fresh_int(nx_);
         float v[P][L];
         Rsrc ri[P], ro[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const int pl = min(pg + p, nplanes - 1);
-            ri[p] = make_rsrc(in + pl * plane, (uint32_t)(plane * 4));
-            ro[p] = make_rsrc(out + pl * plane, pg + p < nplanes ? (uint32_t)(plane * 4) : 0u);
+            ri[p] = make_rsrc(in + (pl0 + p) * plane, (uint32_t)(plane * 4));
+            ro[p] = make_rsrc(out + (pl0 + p) * plane, (uint32_t)(plane * 4));
         }
         {
             // running row offset (a chain, so the compiler keeps one of them live)
@@ -608,58 +595,94 @@ __device__ __forceinline__ void y_block(const float *in, float *out, const float
                 bsh[sw][w][p][lane * 3 + 2] = x[p].c;
             }
             __syncthreads();
+            // chain over the chunks before mine, nearest last: c <- Phi_k c + b_k
+            // (Phi_k read once for all planes)
+            St c[P];
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                St c{0.f, 0.f, 0.f};
-                const int k_lo = desc ? w + 1 : 0, k_hi = desc ? kYWaves : w;
-                for (int kk = k_lo; kk < k_hi; ++kk) {
-                    const int k = desc ? k_hi - 1 - (kk - k_lo) : kk;   // nearest chunk last
-                    float A[9];
+            for (int p = 0; p < P; ++p) c[p] = St{0.f, 0.f, 0.f};
+            const int k_lo = desc ? w + 1 : 0, k_hi = desc ? kYWaves : w;
+            for (int kk = k_lo; kk < k_hi; ++kk) {
+                const int k = desc ? k_hi - 1 - (kk - k_lo) : kk;
+                float A[9];
 #pragma unroll
-                    for (int e = 0; e < 9; ++e) A[e] = phi[sw][k][lane * 9 + e];
+                for (int e = 0; e < 9; ++e) A[e] = phi[sw][k][lane * 9 + e];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
                     St n{bsh[sw][k][p][lane * 3], bsh[sw][k][p][lane * 3 + 1], bsh[sw][k][p][lane * 3 + 2]};
-                    mat_acc(A, c, n);
-                    c = n;
+                    mat_acc(A, c[p], n);
+                    c[p] = n;
                 }
-                x[p] = c;
             }
+#pragma unroll
+            for (int p = 0; p < P; ++p) x[p] = c[p];
             pass(x, DC, std::integral_constant<int, 2>{});
         };
         sweep(std::false_type{});
         sweep(std::true_type{});
-        __syncthreads();   // bsh is rewritten by the next plane group
     }
 }
 
-template <int L, bool ADJ, int P>
+// Planes [pa, pb) of one column block: units of two planes (one when L > 45),
+// and a one-plane unit for an odd count, run first when single_first is set
+// (so that neighbouring workgroups do not reach their memory phases together).
+template <int L, bool ADJ>
+__device__ __forceinline__ void y_planes(const float *in, float *out, const float4 *T, const uint64_t *LM,
+                                         const float *PHI, int nx, int ny, int blk, int pa, int pb,
+                                         bool single_first, float (*phi)[kYWaves][kYCols * 9], float *bsh)
+{
+    constexpr int PM = y_planes_per_lane(L);
+    {
+        const int k0 = ADJ ? 2 : 0;
+        for (int e = threadIdx.x; e < 2 * kYWaves * kYCols; e += 64 * kYWaves) {
+            const int sw = e / (kYWaves * kYCols), rest = e % (kYWaves * kYCols);
+            const float *src = PHI + (((long)blk * 4 + k0 + sw) * kYWaves * kYCols + rest) * 12;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) phi[sw][rest / kYCols][(rest % kYCols) * 9 + q] = src[q];
+        }
+    }
+    __syncthreads();
+    if (PM == 2 && single_first && ((pb - pa) & 1)) {
+        y_unit<L, ADJ, 1>(in, out, T, LM, nx, ny, blk, pa, phi, bsh);
+        ++pa;
+        __syncthreads();   // bsh is rewritten by the next unit
+    }
+    for (; pa + PM <= pb; pa += PM) {
+        y_unit<L, ADJ, PM>(in, out, T, LM, nx, ny, blk, pa, phi, bsh);
+        __syncthreads();
+    }
+    if (pa < pb) y_unit<L, ADJ, 1>(in, out, T, LM, nx, ny, blk, pa, phi, bsh);
+}
+
+// Workgroup (column block, slot): slot j of S takes planes [j n / S, (j+1) n / S).
+template <int L, bool ADJ>
 __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float *out, const float4 *T,
                                                          const uint64_t *__restrict__ LM,
                                                          const float *__restrict__ PHI, int nx, int ny,
-                                                         int nplanes, int nblk, int ngrp)
+                                                         int nplanes, int nblk, int nslot)
 {
     __shared__ float phi[2][kYWaves][kYCols * 9];
-    __shared__ float bsh[2][kYWaves][P][kYCols * 3];
-    // XCD-aware order: all plane groups of a column block run on one XCD (shared L2)
+    __shared__ float bsh[2 * kYWaves * 2 * kYCols * 3];
+    // XCD-aware order: all slots of a column block run on one XCD (shared L2)
     const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
-    const int blk = (slot / ngrp) * 8 + xcd, grp = slot % ngrp;
+    const int blk = (slot / nslot) * 8 + xcd, j = slot % nslot;
     if (blk >= nblk) return;
-    y_block<L, ADJ, P>(in, out, T, LM, PHI, nx, ny, nplanes, blk, grp, ngrp, (nplanes + P - 1) / P, phi, bsh);
+    const int pa = (int)((long)j * nplanes / nslot), pb = (int)((long)(j + 1) * nplanes / nslot);
+    y_planes<L, ADJ>(in, out, T, LM, PHI, nx, ny, blk, pa, pb, (j & 1) != 0, phi, bsh);
 }
 
-// Batched form: one workgroup per work unit {item, column block, first and end plane group}.
-template <int L, bool ADJ, int P>
+// Batched form: one workgroup per work unit {item, column block, first and end plane}.
+template <int L, bool ADJ>
 __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_batch(const BatchEntry *__restrict__ E,
                                                                const BatchUnit *__restrict__ U, int src_out)
 {
     __shared__ float phi[2][kYWaves][kYCols * 9];
-    __shared__ float bsh[2][kYWaves][P][kYCols * 3];
+    __shared__ float bsh[2 * kYWaves * 2 * kYCols * 3];
     const BatchUnit *up = U + blockIdx.x;
     const int item = uni(up->item);
     if (item < 0) return;
     const BatchEntry *e = E + item;
-    y_block<L, ADJ, P>(uni(src_out ? (const float *)e->out : e->in), uni(e->out), uni(e->T[1]), uni(e->LM[1]),
-                       uni(e->PHI[1]), uni(e->nx), uni(e->ny), uni(e->nplanes), uni(up->a), uni(up->b), 1, uni(up->c),
-                       phi, bsh);
+    y_planes<L, ADJ>(uni(src_out ? (const float *)e->out : e->in), uni(e->out), uni(e->T[1]), uni(e->LM[1]),
+                     uni(e->PHI[1]), uni(e->nx), uni(e->ny), uni(up->a), uni(up->b), uni(up->c), false, phi, bsh);
 }
 
 // ---------------------------------------------------------------- setup
@@ -761,8 +784,6 @@ int x_groups(int ny, int nplanes)
     return groups;
 }
 
-int y_planes_per_unit_group(int ly) { return y_planes_per_lane(ly); }
-
 template <int L, bool ADJ>
 static hipError_t launch_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
                            int nx, int ny, int nplanes, hipStream_t st)
@@ -787,26 +808,35 @@ static int cu_count()
     return cache[dev];
 }
 
+// time of a one-plane y unit relative to a two-plane one with every CU busy
+// (measured on 1440 x 720 grids: the memory phases dominate both)
+constexpr double kYSingleCost = 0.85;
+
+// cost of a y workgroup with n planes, in two-plane units
+static double y_range_cost(int n, int pm)
+{
+    return pm == 2 ? n / 2 + (n & 1) * kYSingleCost : n;
+}
+
 template <int L, bool ADJ>
 static hipError_t launch_y(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
                            int nx, int ny, int nplanes, hipStream_t st)
 {
-    constexpr int P = y_planes_per_lane(L);
-    static_assert(P == 1 || P == 2, "planes per lane");
+    constexpr int PM = y_planes_per_lane(L);
+    static_assert(PM == 1 || PM == 2, "planes per lane");
     const int nblk = (nx + kYCols - 1) / kYCols;
-    const int npg = (nplanes + P - 1) / P;   // plane groups
-    // groups per column block: one workgroup per CU at a time, so minimise
-    // (rounds of workgroups) x (plane groups per workgroup)
+    // slots (workgroups) per column block: one workgroup per CU at a time, so
+    // minimise (rounds of workgroups) x (cost of the largest plane range)
     const int cus = cu_count(), nb8 = ((nblk + 7) / 8) * 8;
     int best = 1;
-    long best_cost = -1;
-    for (int g = 1; g <= npg; ++g) {
-        const long rounds = ((long)nb8 * g + cus - 1) / cus;
-        const long cost = rounds * ((npg + g - 1) / g);
-        if (best_cost < 0 || cost < best_cost) { best_cost = cost; best = g; }
+    double best_cost = -1;
+    for (int sl = 1; sl <= nplanes; ++sl) {
+        const long rounds = ((long)nb8 * sl + cus - 1) / cus;
+        const double cost = rounds * y_range_cost((nplanes + sl - 1) / sl, PM);
+        if (best_cost < 0 || cost < best_cost - 1e-9) { best_cost = cost; best = sl; }
     }
     const unsigned nb = (unsigned)(nb8 * best);
-    k_rf3y<L, ADJ, P><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, nblk, best);
+    k_rf3y<L, ADJ><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, nblk, best);
     return hipGetLastError();
 }
 
@@ -850,8 +880,8 @@ hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const uint64
         return hipGetLastError();
 #define RF_YB_CASE(Lv)                                                                                    \
     case Lv:                                                                                              \
-        if (adj) k_rf3y_batch<Lv, true, y_planes_per_lane(Lv)><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out); \
-        else k_rf3y_batch<Lv, false, y_planes_per_lane(Lv)><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out);   \
+        if (adj) k_rf3y_batch<Lv, true><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out);                  \
+        else k_rf3y_batch<Lv, false><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out);                     \
         return hipGetLastError();
 
 hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int lx, bool adj, bool src_out,

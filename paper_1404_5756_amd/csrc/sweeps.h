@@ -37,7 +37,6 @@ hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits,
 hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int ly, bool adj, bool src_out,
                             hipStream_t st);
 int x_groups(int ny, int nplanes);
-int y_planes_per_unit_group(int ly);
 hipError_t setup_phi_y(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int ly, hipStream_t st);
 hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int lx, hipStream_t st);
 }  // namespace rf

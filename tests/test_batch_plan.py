@@ -47,10 +47,8 @@ def _expected_units(items):
         groups.setdefault((0, _tile_lx(g.nx)), 0)
         groups[(0, _tile_lx(g.nx))] += g.ny * _x_groups(g.ny, nplanes)
         ly = _tile_ly(g.ny)
-        p = 2 if ly <= 45 else 1
-        npg = -(-nplanes // p)
         groups.setdefault((1, ly), 0)
-        groups[(1, ly)] += -(-g.nx // 64) * -(-npg // 4)
+        groups[(1, ly)] += -(-g.nx // 64) * -(-nplanes // 8)   # units of up to 8 planes
     return groups
 
 
@@ -61,7 +59,7 @@ def test_plan_header_and_unit_count():
     assert nb > 0 and nb % 256 == 0
     buf = rf3.rf3_batch_plan(items)
     magic, version, n_items, n_units, off_e, off_u, total = struct.unpack_from("<IIiiQQQ", buf, 0)
-    assert magic == 0x50424652 and version == 1
+    assert magic == 0x50424652 and version == 2
     assert n_items == len(items) and total == nb == len(buf)
     exp = _expected_units(items)
     lo = sum(exp.values())
@@ -79,7 +77,7 @@ def test_plan_header_and_unit_count():
     assert len(real) == lo
 
 
-def test_units_cover_every_row_and_plane_group_once():
+def test_units_cover_every_row_and_plane_once():
     items = [_item(0, 257, 131, 5), _item(1, 70, 801, 3), _item(2, 1100, 40, 1, nfields=3)]
     buf = rf3.rf3_batch_plan(items)
     _m, _v, _n, n_units, _oe, off_u, _t = struct.unpack_from("<IIiiQQQ", buf, 0)
@@ -93,10 +91,9 @@ def test_units_cover_every_row_and_plane_group_once():
         rows = sorted((u[1], u[2]) for u in xu if u[0] == k)
         assert rows == [(r, q) for r in range(g.ny) for q in range(groups)]
         assert all(u[3] == groups for u in xu if u[0] == k)
-        ly = _tile_ly(g.ny)
-        npg = -(-g.nlev * nf // (2 if ly <= 45 else 1))
+        # y units: {item, column block, first plane, end plane}
         cover = sorted((u[1], q) for u in yu if u[0] == k for q in range(u[2], u[3]))
-        assert cover == [(b, q) for b in range(-(-g.nx // 64)) for q in range(npg)]
+        assert cover == [(b, q) for b in range(-(-g.nx // 64)) for q in range(g.nlev * nf)]
 
 
 def test_plan_errors():

@@ -108,7 +108,8 @@ __device__ __forceinline__ void fwd_step(St &x, float gs, float gm, float c2, fl
 }
 
 // transposed step at point j (own coefficients), r = input; returns the output
-// beta_j * u before the reset of the state
+// beta_j * u before the reset of the state (OUT), or nothing (local passes)
+template <bool OUT>
 __device__ __forceinline__ float adj_step(St &x, float r, float bt, float gm, float c2, float c3)
 {
     const float w0 = x.a + r;
@@ -116,6 +117,7 @@ __device__ __forceinline__ float adj_step(St &x, float r, float bt, float gm, fl
     x.a = fmaf(-gm, u, w0);
     x.b = fmaf(-c2, u, x.c);
     x.c = -c3 * u;
+    if (!OUT) return 0.f;
     float o = bt * u;
     asm volatile("" : "+v"(o));   // evaluate now: deferring it keeps u and beta live for many steps
     return o;
@@ -183,7 +185,9 @@ struct XRow {
     mask_ptr lm;                               // this row's masks: [3][LP] FRESET, BRESET, not-SEA
 
     // ascending sweep over my chunk.  MODE 1: input v, no output;
-    // MODE 2: input v, output written back into v.
+    // MODE 2: input v, output written back into v.  Forward inputs are beta_i s_i
+    // (formed once for both passes), and the forward output is beta_i u_i, the
+    // input of the anti-causal passes.
     template <int MODE>
     __device__ __forceinline__ void asc(St &x, float *v) const
     {
@@ -195,10 +199,10 @@ struct XRow {
             const uint64_t m = rp[i];
             if (!ADJ) {
                 st_reset(x, m);
-                fwd_step(x, kb[i] * v[i], kg[i], k2[i], k3[i]);
-                if (MODE == 2) v[i] = x.a;
+                fwd_step(x, v[i], kg[i], k2[i], k3[i]);
+                if (MODE == 2) v[i] = kb[i] * x.a;
             } else {
-                const float o = adj_step(x, v[i], kb[i], kg[i], k2[i], k3[i]);
+                const float o = adj_step<MODE == 2>(x, v[i], kb[i], kg[i], k2[i], k3[i]);
                 st_reset(x, m);
                 if (MODE == 2) v[i] = o;
             }
@@ -217,10 +221,10 @@ struct XRow {
             const uint64_t m = rp[i];
             if (!ADJ) {
                 st_reset(x, m);
-                fwd_step(x, kb[i] * v[i], kg[i], k2[i], k3[i]);
+                fwd_step(x, v[i], kg[i], k2[i], k3[i]);
                 if (MODE == 2) v[i] = zero_if(x.a, sp[i]);
             } else {
-                const float o = adj_step(x, v[i], kb[i], kg[i], k2[i], k3[i]);
+                const float o = adj_step<MODE == 2>(x, v[i], kb[i], kg[i], k2[i], k3[i]);
                 st_reset(x, m);
                 if (MODE == 2) v[i] = zero_if(o, sp[i]);
             }
@@ -392,7 +396,10 @@ __device__ __forceinline__ void x_rows(const float *in, float *out, const float4
         {
             mask_ptr sp = R.lm + 2 * XRow<L, ADJ>::LP + fresh_int(0);
 #pragma unroll
-            for (int i = 0; i < L; ++i) v[i] = zero_if(v[i], sp[i]);   // input only at sea points
+            for (int i = 0; i < L; ++i) {
+                v[i] = zero_if(v[i], sp[i]);   // input only at sea points
+                if (!ADJ) v[i] = R.kb[i] * v[i];
+            }
         }
         St x{0.f, 0.f, 0.f};
         R.template asc<1>(x, v);
@@ -556,17 +563,21 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
                     const uint64_t mm = m64_of(m, q);
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        if (first) v[p][i] = zero_if(v[p][i], m64_of(sm, q));   // input only at sea points
+                        if (first) {   // input only at sea points; forward: beta_i s_i for both passes
+                            v[p][i] = zero_if(v[p][i], m64_of(sm, q));
+                            if (!ADJ) v[p][i] = bt * v[p][i];
+                        }
                         float o;
                         if (!ADJ) {
                             st_reset(x[p], mm);
-                            fwd_step(x[p], bt * v[p][i], gm, c2, c3);
+                            fwd_step(x[p], v[p][i], gm, c2, c3);
                             o = x[p].a;
                         } else {
-                            o = adj_step(x[p], v[p][i], bt, gm, c2, c3);
+                            o = adj_step<mode == 2>(x[p], v[p][i], bt, gm, c2, c3);
                             st_reset(x[p], mm);
                         }
-                        if (mode == 2) v[p][i] = desc ? zero_if(o, m64_of(sm, q)) : o;
+                        // forward ascending output: beta_i u_i, the anti-causal input
+                        if (mode == 2) v[p][i] = desc ? zero_if(o, m64_of(sm, q)) : (ADJ ? o : bt * o);
                     }
                     if (last) {
                         if (soff < lim) {   // rows past the grid are not stored

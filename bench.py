@@ -35,18 +35,21 @@ def log(msg):
 
 
 def bench_batch(torch, dev, args):
-    """64 uneven grids (C4) in one batch: forward + adjoint, against one call per grid."""
+    """64 uneven grids (C4) in one batch: forward + adjoint, against one call per grid.
+    The work-list shape is autotuned on the items; the tuned batch is also timed as
+    hipGraph replays of one captured forward + adjoint."""
     from paper_1404_5756_amd import synth
     from paper_1404_5756_amd.operator import Batch, HorizontalCovariance
     ws = synth.c4_batch()
     gen = torch.Generator(device=dev).manual_seed(synth.SEEDS["c4"])
     t0 = time.time()
-    ops, xs = [], []
+    ops, xs, ys = [], [], []
     for w in ws:
         ops.append(HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode,
                                         device=dev))
         xs.append(torch.randn((1, w.nlev, w.ny, w.nx), generator=gen, device=dev))
-    b = Batch([(op, x, x) for op, x in zip(ops, xs)])   # in place
+        ys.append(torch.empty_like(xs[-1]))
+    b = Batch([(op, x, y) for op, x, y in zip(ops, xs, ys)])
     torch.cuda.synchronize()
     setup = time.time() - t0
     pts = b.points
@@ -64,14 +67,28 @@ def bench_batch(torch, dev, args):
         return e0.elapsed_time(e1) / reps
 
     reps = max(3, args.steps // 4)
-    ms_b = timed(lambda: (b.apply(False), b.apply(True)), reps)
-    ms_i = timed(lambda: [(op.apply(x, out=x), op.adjoint(x, out=x)) for op, x in zip(ops, xs)], reps)
-    log(f"batch C4: {len(ws)} grids, {pts / 1e9:.3f} G points: batched fwd+adj {ms_b:.2f} ms, "
-        f"per-grid calls {ms_i:.2f} ms (setup {setup:.1f} s)")
+    ms_default = timed(lambda: (b.apply(False), b.apply(True)), reps)
+    ms_i = timed(lambda: [(op.apply(x, out=y), op.adjoint(x, out=y)) for op, x, y in zip(ops, xs, ys)], reps)
+    t1 = time.time()
+    tune_times = b.autotune(reps=2)
+    tune_s = time.time() - t1
+    ms_tuned = timed(lambda: (b.apply(False), b.apply(True)), reps)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.apply(False)
+        b.apply(True)
+    ms_graph = timed(g.replay, max(reps, 10))
+    ms_b = min(ms_tuned, ms_graph)
+    log(f"batch C4: {len(ws)} grids, {pts / 1e9:.3f} G points: fwd+adj default shape {ms_default:.2f} ms, "
+        f"autotuned {b.tuning} {ms_tuned:.2f} ms, graph replay {ms_graph:.2f} ms; per-grid calls {ms_i:.2f} ms "
+        f"(setup {setup:.1f} s, autotune {tune_s:.1f} s over {len(tune_times)} shapes)")
     res = {"grids": len(ws), "points": pts, "ms_fwd_adj": round(ms_b, 3),
-           "gpoints_s": round(pts / (ms_b * 1e-3) / 1e9, 2), "ms_per_grid_calls": round(ms_i, 3),
-           "speedup_vs_per_grid_calls": round(ms_i / ms_b, 3), "setup_s": round(setup, 1)}
-    del b, ops, xs
+           "gpoints_s": round(pts / (ms_b * 1e-3) / 1e9, 2), "ms_default_shape": round(ms_default, 3),
+           "ms_autotuned": round(ms_tuned, 3), "ms_graph_replay": round(ms_graph, 3),
+           "tuning": {"x_groups_max": b.tuning[0], "y_planes": b.tuning[1]} if b.tuning else "default",
+           "ms_per_grid_calls": round(ms_i, 3), "speedup_vs_per_grid_calls": round(ms_i / ms_b, 3),
+           "setup_s": round(setup, 1), "autotune_s": round(tune_s, 1)}
+    del g, b, ops, xs, ys
     torch.cuda.empty_cache()
     return res
 

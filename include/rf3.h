@@ -166,6 +166,25 @@ int rf3_batch_plan(const rf_batch_item *items, int32_t n, void *plan, size_t pla
 int rf3_apply_batch(const rf_batch_item *items, int32_t n, rf_prec prec, int32_t adjoint,
                     const void *plan_dev, size_t plan_bytes, void *stream);
 
+/* Work-list shape of a batch.  A zero field selects its default; the calls
+ * above use the defaults.  The best shape depends on the items (their sizes
+ * and level counts), so the Python binding's Batch.autotune times candidate
+ * shapes on the actual items and keeps the fastest.  Results do not depend on
+ * the shape (bitwise).  Out-of-range values give 0 / RF_E_ARG.  The _ex calls
+ * behave as the plain ones; rf3_apply_batch_ex must get the tuning the plan
+ * was built with (a different one is undefined, like other items). */
+typedef struct {
+    int32_t x_groups_max;   /* max workgroups sharing the planes of one x row, 1..64 (a power of two
+                               is used: the largest not above it); default 8 */
+    int32_t y_planes;       /* planes per y work unit (one workgroup), 1..4096; default 8 */
+} rf_batch_tuning;
+
+size_t rf3_batch_plan_bytes_ex(const rf_batch_item *items, int32_t n, const rf_batch_tuning *t);
+int rf3_batch_plan_ex(const rf_batch_item *items, int32_t n, const rf_batch_tuning *t, void *plan,
+                      size_t plan_bytes);
+int rf3_apply_batch_ex(const rf_batch_item *items, int32_t n, const rf_batch_tuning *t, rf_prec prec,
+                       int32_t adjoint, const void *plan_dev, size_t plan_bytes, void *stream);
+
 /* 3D-VAR harness: bilinear observation operator H and its adjoint H^T.
  * The minimiser of Sec. 2 needs V and V^T (above) and the observation
  * operator with its transpose in every iteration.  Observation o is at level

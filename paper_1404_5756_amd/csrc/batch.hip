@@ -18,9 +18,26 @@ namespace {
 
 constexpr uint32_t kPlanMagic = 0x50424652u;   // "RFBP"
 constexpr uint32_t kPlanVersion = 2;
-// planes per y work unit: the unit's setup (transfer matrices into LDS) is
-// shared by this many planes of its column block
+// default planes per y work unit: the unit's setup (transfer matrices into
+// LDS) is shared by this many planes of its column block
 constexpr int kYPlanesPerUnit = 8;
+// default cap on the workgroups that share one x row of an item
+constexpr int kXGroupsMax = 8;
+
+struct Tuning {
+    int x_groups_max, y_planes;
+};
+
+// the work-list shape: defaults for zero fields; false on values out of range
+bool tuning_of(const rf_batch_tuning *t, Tuning &o)
+{
+    o = Tuning{kXGroupsMax, kYPlanesPerUnit};
+    if (!t) return true;
+    if (t->x_groups_max < 0 || t->x_groups_max > 64 || t->y_planes < 0 || t->y_planes > 4096) return false;
+    if (t->x_groups_max) o.x_groups_max = t->x_groups_max;
+    if (t->y_planes) o.y_planes = t->y_planes;
+    return true;
+}
 
 struct PlanHeader {
     uint32_t magic, version;
@@ -65,9 +82,10 @@ void emit_xcd(const std::vector<std::vector<BatchUnit>> &clusters, std::vector<B
         for (int x = 0; x < 8; ++x) out.push_back(i < q[x].size() ? q[x][i] : BatchUnit{-1, 0, 0, 0});
 }
 
-int build(const rf_batch_item *items, int32_t n, HostPlan &P)
+int build(const rf_batch_item *items, int32_t n, const rf_batch_tuning *tuning, HostPlan &P)
 {
-    if (!items || n < 1) return RF_E_ARG;
+    Tuning tu;
+    if (!items || n < 1 || !tuning_of(tuning, tu)) return RF_E_ARG;
     std::map<int, std::vector<std::vector<BatchUnit>>> xc, yc;   // tile size -> clusters
     P.entries.assign(n, BatchEntry{});
     const bool seq_all = force_sequential();
@@ -97,20 +115,20 @@ int build(const rf_batch_item *items, int32_t n, HostPlan &P)
         e.PHI[0] = at<const float>(it.coef, h.off_phix);
         e.PHI[1] = at<const float>(it.coef, h.off_phiy);
         // x: one cluster per row, its `groups` units take interleaved planes
-        const int groups = x_groups(g->ny, (int)nplanes);
+        const int groups = x_groups(g->ny, (int)nplanes, tu.x_groups_max);
         auto &xl = xc[h.lx];
         for (int r = 0; r < g->ny; ++r) {
             std::vector<BatchUnit> c;
             for (int k = 0; k < groups; ++k) c.push_back(BatchUnit{i, r, k, groups});
             xl.push_back(std::move(c));
         }
-        // y: one cluster per column block, units of kYPlanesPerUnit planes [b, c)
+        // y: one cluster per column block, units of up to tu.y_planes planes [b, c)
         const int nblk = (g->nx + kYCols - 1) / kYCols;
         auto &yl = yc[h.ly];
         for (int b = 0; b < nblk; ++b) {
             std::vector<BatchUnit> c;
-            for (int p0 = 0; p0 < nplanes; p0 += kYPlanesPerUnit)
-                c.push_back(BatchUnit{i, b, p0, (int)std::min<long>(nplanes, p0 + kYPlanesPerUnit)});
+            for (long p0 = 0; p0 < nplanes; p0 += tu.y_planes)
+                c.push_back(BatchUnit{i, b, (int)p0, (int)std::min<long>(nplanes, p0 + tu.y_planes)});
             yl.push_back(std::move(c));
         }
     }
@@ -129,17 +147,23 @@ int build(const rf_batch_item *items, int32_t n, HostPlan &P)
 
 }  // namespace
 
-extern "C" size_t rf3_batch_plan_bytes(const rf_batch_item *items, int32_t n)
+extern "C" size_t rf3_batch_plan_bytes_ex(const rf_batch_item *items, int32_t n, const rf_batch_tuning *t)
 {
     HostPlan P;
-    if (build(items, n, P) != RF_OK) return 0;
+    if (build(items, n, t, P) != RF_OK) return 0;
     return P.total_bytes;
 }
 
-extern "C" int rf3_batch_plan(const rf_batch_item *items, int32_t n, void *plan, size_t plan_bytes)
+extern "C" size_t rf3_batch_plan_bytes(const rf_batch_item *items, int32_t n)
+{
+    return rf3_batch_plan_bytes_ex(items, n, nullptr);
+}
+
+extern "C" int rf3_batch_plan_ex(const rf_batch_item *items, int32_t n, const rf_batch_tuning *t, void *plan,
+                                 size_t plan_bytes)
 {
     HostPlan P;
-    const int rc = build(items, n, P);
+    const int rc = build(items, n, t, P);
     if (rc) return rc;
     if (!plan || plan_bytes != P.total_bytes) return RF_E_ARG;
     memset(plan, 0, plan_bytes);
@@ -157,11 +181,17 @@ extern "C" int rf3_batch_plan(const rf_batch_item *items, int32_t n, void *plan,
     return RF_OK;
 }
 
-extern "C" int rf3_apply_batch(const rf_batch_item *items, int32_t n, rf_prec prec, int32_t adjoint,
-                               const void *plan_dev, size_t plan_bytes, void *stream)
+extern "C" int rf3_batch_plan(const rf_batch_item *items, int32_t n, void *plan, size_t plan_bytes)
+{
+    return rf3_batch_plan_ex(items, n, nullptr, plan, plan_bytes);
+}
+
+extern "C" int rf3_apply_batch_ex(const rf_batch_item *items, int32_t n, const rf_batch_tuning *t, rf_prec prec,
+                                  int32_t adjoint, const void *plan_dev, size_t plan_bytes, void *stream)
 {
     const bool adj = adjoint != 0;
-    if (prec != RF_FP32 && prec != RF_FP64) return RF_E_ARG;
+    Tuning tu;
+    if ((prec != RF_FP32 && prec != RF_FP64) || !tuning_of(t, tu)) return RF_E_ARG;
     if (prec == RF_FP64) {   // no FP64 tiled kernels: one application per item
         if (!items || n < 1) return RF_E_ARG;
         for (int i = 0; i < n; ++i) {
@@ -178,7 +208,7 @@ extern "C" int rf3_apply_batch(const rf_batch_item *items, int32_t n, rf_prec pr
         return RF_OK;
     }
     HostPlan P;
-    const int rc = build(items, n, P);
+    const int rc = build(items, n, t, P);
     if (rc) return rc;
     if (!plan_dev || plan_bytes != P.total_bytes || reinterpret_cast<uintptr_t>(plan_dev) % 256) return RF_E_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -200,4 +230,10 @@ extern "C" int rf3_apply_batch(const rf_batch_item *items, int32_t n, rf_prec pr
         if (r) return r;
     }
     return RF_OK;
+}
+
+extern "C" int rf3_apply_batch(const rf_batch_item *items, int32_t n, rf_prec prec, int32_t adjoint,
+                               const void *plan_dev, size_t plan_bytes, void *stream)
+{
+    return rf3_apply_batch_ex(items, n, nullptr, prec, adjoint, plan_dev, plan_bytes, stream);
 }

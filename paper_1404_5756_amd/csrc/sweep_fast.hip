@@ -787,11 +787,12 @@ __global__ void k_phi_x(const float4 *__restrict__ T, const uint8_t *__restrict_
 
 // ---------------------------------------------------------------- dispatch
 // groups per row for the x kernel: enough workgroups to cover the chip several
-// times, at least two lines per wave
-int x_groups(int ny, int nplanes)
+// times, at least two lines per wave, at most gmax
+int x_groups(int ny, int nplanes, int gmax)
 {
     int groups = 1;
-    while (groups < 8 && (long)((ny + 7) / 8) * 8 * groups < 2048 && groups * kXWaves * 2 <= nplanes) groups *= 2;
+    while (groups * 2 <= gmax && (long)((ny + 7) / 8) * 8 * groups < 2048 && groups * kXWaves * 2 <= nplanes)
+        groups *= 2;
     return groups;
 }
 
@@ -799,7 +800,7 @@ template <int L, bool ADJ>
 static hipError_t launch_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
                            int nx, int ny, int nplanes, hipStream_t st)
 {
-    const int groups = x_groups(ny, nplanes);
+    const int groups = x_groups(ny, nplanes, 8);
     const unsigned nb = (unsigned)(((ny + 7) / 8) * 8 * groups);
     k_rf3x<L, ADJ><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups);
     return hipGetLastError();

@@ -36,7 +36,7 @@ hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits,
                             hipStream_t st);
 hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int ly, bool adj, bool src_out,
                             hipStream_t st);
-int x_groups(int ny, int nplanes);
+int x_groups(int ny, int nplanes, int gmax);
 hipError_t setup_phi_y(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int ly, hipStream_t st);
 hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int lx, hipStream_t st);
 }  // namespace rf

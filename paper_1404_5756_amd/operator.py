@@ -103,9 +103,14 @@ class Batch:
     items: [(HorizontalCovariance, x, y)] with x, y FP32 device tensors
     [nfields][op.nlev][ny][nx] (y may be x).  The work list is built once here
     and kept on the device; build a new Batch when any tensor changes.
+    tuning: None (default work-list shape) or (x_groups_max, y_planes), see
+    rf_batch_tuning; autotune() picks one by timing.
     """
 
-    def __init__(self, items, device=None):
+    # candidate work-list shapes tried by autotune(): (x_groups_max, y_planes)
+    CANDIDATES = tuple((xg, yp) for xg in (1, 2, 4, 8, 16) for yp in (1, 2, 4, 8, 16))
+
+    def __init__(self, items, device=None, tuning=None):
         self._items = []
         self._keep = []
         for op, x, y in items:
@@ -117,14 +122,41 @@ class Batch:
                 raise ValueError("batched fields must be contiguous")
             self._items.append((op.grid, op.coef, x, y, x.shape[0]))
             self._keep.append((op, x, y))
-        host = rf3.rf3_batch_plan(self._items)
-        dev = device if device is not None else self._items[0][2].device
+        self.device = device if device is not None else self._items[0][2].device
+        self._set_tuning(tuning)
+
+    def _set_tuning(self, tuning):
+        self.tuning = None if tuning is None else (int(tuning[0]), int(tuning[1]))
+        host = rf3.rf3_batch_plan(self._items, self.tuning)
         # torch's caching allocator returns 512-byte aligned blocks
-        self.plan = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(dev)
+        self.plan = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(self.device)
 
     @property
     def points(self):
         return sum(x.numel() for _, x, _ in self._keep)
 
     def apply(self, adjoint=False, stream=None):
-        rf3.rf3_apply_batch(self._items, rf3.RF_FP32, int(bool(adjoint)), self.plan, self.plan.numel(), stream)
+        rf3.rf3_apply_batch(self._items, rf3.RF_FP32, int(bool(adjoint)), self.plan, self.plan.numel(), stream,
+                            self.tuning)
+
+    def autotune(self, candidates=None, reps=3):
+        """Time forward + adjoint for each candidate work-list shape on these items
+        and keep the fastest.  The batch is applied repeatedly: the items' outputs
+        (and inputs, for items applied in place) are overwritten.  Returns
+        {shape: ms} with the default shape under the key None."""
+        stream = torch.cuda.current_stream(self.device)
+        times = {}
+        for t in [None] + list(candidates if candidates is not None else self.CANDIDATES):
+            self._set_tuning(t)
+            self.apply(False)
+            self.apply(True)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                self.apply(False)
+                self.apply(True)
+            b.record(stream)
+            b.synchronize()
+            times[t] = a.elapsed_time(b) / reps
+        self._set_tuning(min(times, key=times.get))
+        return times

@@ -35,6 +35,13 @@ class rf_batch_item(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("nfields", ctypes.c_int32)]
 
 
+class rf_batch_tuning(ctypes.Structure):
+    _fields_ = [("x_groups_max", ctypes.c_int32), ("y_planes", ctypes.c_int32)]
+
+    def __repr__(self):
+        return f"rf_batch_tuning(x_groups_max={self.x_groups_max}, y_planes={self.y_planes})"
+
+
 class RFError(RuntimeError):
     def __init__(self, status, where):
         super().__init__(f"{where}: {rf_strerror(status)} (status {status})")
@@ -72,6 +79,13 @@ def lib() -> ctypes.CDLL:
         L.rf3_batch_plan.argtypes = [B, I, P, S]
         L.rf3_apply_batch.restype = I
         L.rf3_apply_batch.argtypes = [B, I, I, I, P, S, P]
+        T = ctypes.POINTER(rf_batch_tuning)
+        L.rf3_batch_plan_bytes_ex.restype = S
+        L.rf3_batch_plan_bytes_ex.argtypes = [B, I, T]
+        L.rf3_batch_plan_ex.restype = I
+        L.rf3_batch_plan_ex.argtypes = [B, I, T, P, S]
+        L.rf3_apply_batch_ex.restype = I
+        L.rf3_apply_batch_ex.argtypes = [B, I, T, I, I, P, S, P]
         D = ctypes.POINTER(ctypes.c_double)
         IP = ctypes.POINTER(ctypes.c_int32)
         L.rf_obs_plan_bytes.restype = S
@@ -168,26 +182,50 @@ def _items(items):
     return arr, keep
 
 
-def rf3_batch_plan_bytes(items) -> int:
+def _tuning(tuning):
+    """None (defaults), an rf_batch_tuning, or a (x_groups_max, y_planes) pair."""
+    if tuning is None or isinstance(tuning, rf_batch_tuning):
+        return tuning
+    xg, yp = tuning
+    return rf_batch_tuning(int(xg), int(yp))
+
+
+def _tptr(t):
+    return ctypes.byref(t) if t is not None else None
+
+
+def rf3_batch_plan_bytes(items, tuning=None) -> int:
     arr, _keep = _items(items)
-    return lib().rf3_batch_plan_bytes(arr, len(items))
+    t = _tuning(tuning)
+    if t is None:
+        return lib().rf3_batch_plan_bytes(arr, len(items))
+    return lib().rf3_batch_plan_bytes_ex(arr, len(items), _tptr(t))
 
 
-def rf3_batch_plan(items) -> bytes:
+def rf3_batch_plan(items, tuning=None) -> bytes:
     """Host work list for `items` [(grid, coef, in, out, nfields), ...]; copy it to the device yourself."""
     arr, _keep = _items(items)
-    nb = lib().rf3_batch_plan_bytes(arr, len(items))
+    t = _tuning(tuning)
+    nb = lib().rf3_batch_plan_bytes_ex(arr, len(items), _tptr(t))
     if nb == 0:
         raise RFError(RF_E_ARG, "rf3_batch_plan_bytes")
     buf = ctypes.create_string_buffer(nb)
-    _check(lib().rf3_batch_plan(arr, len(items), buf, nb), "rf3_batch_plan")
+    if t is None:
+        _check(lib().rf3_batch_plan(arr, len(items), buf, nb), "rf3_batch_plan")
+    else:
+        _check(lib().rf3_batch_plan_ex(arr, len(items), _tptr(t), buf, nb), "rf3_batch_plan_ex")
     return buf.raw
 
 
-def rf3_apply_batch(items, prec, adjoint, plan_dev, plan_bytes, stream=None):
+def rf3_apply_batch(items, prec, adjoint, plan_dev, plan_bytes, stream=None, tuning=None):
     arr, _keep = _items(items)
-    _check(lib().rf3_apply_batch(arr, len(items), int(prec), int(adjoint), _ptr(plan_dev), int(plan_bytes),
-                                 _stream(stream)), "rf3_apply_batch")
+    t = _tuning(tuning)
+    if t is None:
+        _check(lib().rf3_apply_batch(arr, len(items), int(prec), int(adjoint), _ptr(plan_dev), int(plan_bytes),
+                                     _stream(stream)), "rf3_apply_batch")
+    else:
+        _check(lib().rf3_apply_batch_ex(arr, len(items), _tptr(t), int(prec), int(adjoint), _ptr(plan_dev),
+                                        int(plan_bytes), _stream(stream)), "rf3_apply_batch_ex")
 
 
 def rf_obs_plan(g, lev, x, y):

@@ -114,3 +114,40 @@ def test_plan_errors():
     assert rf3.lib().rf3_apply_batch(arr, 1, rf3.RF_FP32, 0, ctypes.c_void_p(FAKE), nb + 256, None) == rf3.RF_E_ARG
     with pytest.raises(rf3.RFError):
         rf3.rf3_batch_plan([])
+
+
+def test_tuning_shapes_the_work_list():
+    g = rf3.make_grid(300, 200, 7)
+    items = [(g, FAKE, FAKE + (1 << 36), FAKE + (1 << 36) + (1 << 31), 3)]   # 21 planes
+    nplanes = 21
+    for xg, yp in ((1, 1), (2, 5), (4, 21), (16, 64), (3, 8)):
+        buf = rf3.rf3_batch_plan(items, (xg, yp))
+        _m, _v, _n, n_units, _oe, off_u, _t = struct.unpack_from("<IIiiQQQ", buf, 0)
+        units = [struct.unpack_from("<iiii", buf, off_u + 16 * k) for k in range(n_units)]
+        real = [u for u in units if u[0] >= 0]
+        cap = 1 << (xg.bit_length() - 1)     # the largest power of two not above x_groups_max
+        groups = 1
+        while groups * 2 <= cap and ((200 + 7) // 8) * 8 * groups < 2048 and groups * 4 * 2 <= nplanes:
+            groups *= 2
+        xu = [u for u in real[:200 * groups]]
+        assert sorted((u[1], u[2]) for u in xu) == [(r, q) for r in range(200) for q in range(groups)]
+        yu = real[200 * groups:]
+        nblk = -(-300 // 64)
+        assert len(yu) == nblk * -(-nplanes // yp)
+        assert all(u[3] - u[2] <= yp for u in yu)
+        cover = sorted((u[1], q) for u in yu for q in range(u[2], u[3]))
+        assert cover == [(b, q) for b in range(nblk) for q in range(nplanes)]
+
+
+def test_tuning_out_of_range_is_refused():
+    g = rf3.make_grid(64, 64, 2)
+    items = [(g, FAKE, FAKE + (1 << 36), FAKE + (1 << 36) + (1 << 31), 1)]
+    for t in ((-1, 0), (0, -1), (65, 0), (0, 4097)):
+        assert rf3.rf3_batch_plan_bytes(items, t) == 0
+        with pytest.raises(rf3.RFError):
+            rf3.rf3_batch_plan(items, t)
+    assert rf3.rf3_batch_plan_bytes(items, (0, 0)) == rf3.rf3_batch_plan_bytes(items)
+    arr, _keep = rf3._items(items)
+    bad = rf3.rf_batch_tuning(0, -3)
+    assert rf3.lib().rf3_apply_batch_ex(arr, 1, ctypes.byref(bad), rf3.RF_FP32, 0, ctypes.c_void_p(FAKE), 256,
+                                        None) == rf3.RF_E_ARG

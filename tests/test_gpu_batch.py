@@ -113,3 +113,44 @@ def test_batch_graph_replays(batch_setup):
         torch.cuda.synchronize()
         for k, (a, e) in enumerate(zip(got, outs)):
             assert torch.equal(a, e), f"replay {rep}, item {k}"
+
+
+def _batch_items(ops, xs):
+    items, outs = [], []
+    for (seed, ny, nx, nlev, nf, m3, ip), op, x in zip(ITEMS, ops, xs):
+        xi = x.clone()
+        y = xi if ip else torch.empty_like(xi)
+        items.append((op, xi, y))
+        outs.append(y)
+    return items, outs
+
+
+@pytest.mark.parametrize("tuning", [(1, 1), (2, 3), (16, 2), (64, 64)])
+def test_batch_tuning_is_bitwise_neutral(batch_setup, tuning):
+    """Any work-list shape gives exactly the default result (same kernels per line)."""
+    ws, ops, xs = batch_setup
+    for adjoint in (False, True):
+        ref = _run_batch(ops, xs, adjoint)
+        items, outs = _batch_items(ops, xs)
+        b = Batch(items, tuning=tuning)
+        b.apply(adjoint=adjoint)
+        torch.cuda.synchronize()
+        for k, (a, e) in enumerate(zip(outs, ref)):
+            assert torch.equal(a, e), f"tuning {tuning}, adjoint {adjoint}, item {k}"
+
+
+def test_batch_autotune(batch_setup):
+    ws, ops, xs = batch_setup
+    items, outs = _batch_items(ops, xs)
+    b = Batch(items)
+    times = b.autotune(candidates=[(2, 2), (8, 16)], reps=1)
+    assert set(times) == {None, (2, 2), (8, 16)} and all(t > 0 for t in times.values())
+    assert b.tuning == min(times, key=times.get)
+    # the tuned batch still computes V_H: rerun on fresh copies of the inputs
+    items2, outs2 = _batch_items(ops, xs)
+    b2 = Batch(items2, tuning=b.tuning)
+    b2.apply()
+    torch.cuda.synchronize()
+    ref = _run_batch(ops, xs, False)
+    for k, (a, e) in enumerate(zip(outs2, ref)):
+        assert torch.equal(a, e), f"item {k}"

@@ -212,6 +212,17 @@ int rf_obs_apply(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t npts
                  void *obs, void *stream);
 int rf_obs_adjoint(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t npts, rf_prec prec, const void *obs,
                    void *field, void *stream);
+/* Weighted innovation of the cost of Sec. 2.1 (eq. `functional2`), in
+ * observation space, with R = diag(1 / rinv):
+ *   d = H field - yobs,   rd = scale * rinv o d
+ * field or yobs may be NULL (that term is 0); rinv may be NULL (weight 1);
+ * d may be NULL (not stored).  rd = R^-1 (H V v - y) for the cost and its
+ * gradient; R^-1 H V p inside CG (yobs NULL); R^-1 y for CG's first residual
+ * (field NULL, scale -1).  Same plan and size rules as rf_obs_apply; vectors
+ * are device arrays of nobs values of `prec`. */
+int rf_obs_innovation(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t npts, rf_prec prec,
+                      const void *field, const void *yobs, const void *rinv, double scale, void *d, void *rd,
+                      void *stream);
 
 /* 3D-VAR harness: vector steps of conjugate gradients (Sec. 2.1 solves its
  * preconditioned system by CG).  The iteration's scalars live in device
@@ -225,6 +236,7 @@ int rf_obs_adjoint(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t np
  *   rf_cg_step:  a = s[RF_CG_RR] / s[RF_CG_PQ] (0 if s[RF_CG_PQ] <= 0);
  *                v += a p;  r -= a q;  s[RF_CG_RR_NEW] = r.r
  *   rf_cg_dir:   p = r + (s[RF_CG_RR_NEW] / s[RF_CG_RR]) p;  s[RF_CG_RR] = s[RF_CG_RR_NEW]
+ *   rf_axpy:     y += a x  (the gradient v + V^T H^T rd, the Hessian product p + w)
  * Asynchronous on `stream`; no allocation.  RF_E_ARG on null pointers,
  * n < 1, a bad precision or slot. */
 enum { RF_CG_RR = 0, RF_CG_PQ = 1, RF_CG_RR_NEW = 2, RF_CG_SLOTS = 8 };
@@ -236,6 +248,7 @@ int rf_cg_q_dot(rf_prec prec, int64_t n, const void *p, const void *w, void *q, 
 int rf_cg_step(rf_prec prec, int64_t n, const void *p, const void *q, void *v, void *r, void *work, double *s,
                void *stream);
 int rf_cg_dir(rf_prec prec, int64_t n, const void *r, void *p, double *s, void *stream);
+int rf_axpy(rf_prec prec, int64_t n, double a, const void *x, void *y, void *stream);
 
 /* Static description of a status code. */
 const char *rf_strerror(int status);

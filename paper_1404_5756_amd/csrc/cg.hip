@@ -96,6 +96,14 @@ __global__ __launch_bounds__(kCgThreads) void k_finish(const double *__restrict_
 
 __global__ void k_set(double *s, int to, int from) { s[to] = s[from]; }
 
+// y += a x
+template <class T>
+__global__ __launch_bounds__(kCgThreads) void k_axpy(T a, const T *__restrict__ x, T *__restrict__ y, long n)
+{
+    for (long i = (long)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += (long)kCgBlocks * kCgThreads)
+        y[i] += a * x[i];
+}
+
 bool args_ok(int prec, long n, const void *a, const void *b)
 {
     return (prec == RF_FP32 || prec == RF_FP64) && n >= 1 && a && b;
@@ -159,5 +167,16 @@ extern "C" int rf_cg_dir(rf_prec prec, int64_t n, const void *r, void *p, double
         k_dir<double><<<kCgBlocks, kCgThreads, 0, st>>>((const double *)r, (double *)p, s, n);
     // rr <- rr_new for the next iteration (after k_dir has read both)
     k_set<<<1, 1, 0, st>>>(s, RF_CG_RR, RF_CG_RR_NEW);
+    return hipGetLastError() == hipSuccess ? RF_OK : RF_E_HIP;
+}
+
+extern "C" int rf_axpy(rf_prec prec, int64_t n, double a, const void *x, void *y, void *stream)
+{
+    if (!args_ok(prec, n, x, y)) return RF_E_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (prec == RF_FP32)
+        k_axpy<float><<<kCgBlocks, kCgThreads, 0, st>>>((float)a, (const float *)x, (float *)y, n);
+    else
+        k_axpy<double><<<kCgBlocks, kCgThreads, 0, st>>>(a, (const double *)x, (double *)y, n);
     return hipGetLastError() == hipSuccess ? RF_OK : RF_E_HIP;
 }

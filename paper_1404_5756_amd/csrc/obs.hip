@@ -119,6 +119,25 @@ __global__ void k_obs_apply(const ObsPlanHeader *__restrict__ hd, const int32_t 
     out[o] = s;
 }
 
+// d = H f - y (a missing term is 0), rd = scale * rinv o d (rinv missing: 1)
+template <class T>
+__global__ void k_obs_innov(const ObsPlanHeader *__restrict__ hd, const int32_t *__restrict__ idx,
+                            const double *__restrict__ w, const T *__restrict__ f, const T *__restrict__ y,
+                            const T *__restrict__ rinv, T scale, T *__restrict__ d, T *__restrict__ rd,
+                            int32_t nobs, int32_t nuniq, int64_t npts)
+{
+    const int32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nobs || !plan_matches(hd, nobs, nuniq, npts)) return;
+    T s = 0;
+    if (f) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s += (T)w[4 * o + c] * f[idx[4 * o + c]];
+    }
+    if (y) s -= y[o];
+    if (d) d[o] = s;
+    rd[o] = (rinv ? rinv[o] : (T)1) * scale * s;
+}
+
 template <class T>
 __global__ void k_fill(T *__restrict__ f, long n)
 {
@@ -231,5 +250,30 @@ extern "C" int rf_obs_adjoint(const void *plan_dev, int32_t nobs, int32_t nuniq,
         k_obs_adjoint<double><<<nb, 256, 0, st>>>(hd, upt, uptr, ent, w, (const double *)obs, (double *)field, nobs,
                                                   nuniq, npts);
     }
+    return hipGetLastError() == hipSuccess ? RF_OK : RF_E_HIP;
+}
+
+extern "C" int rf_obs_innovation(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t npts, rf_prec prec,
+                                 const void *field, const void *yobs, const void *rinv, double scale, void *d,
+                                 void *rd, void *stream)
+{
+    if (!plan_dev || !rd || nobs < 1 || nuniq < 1 || npts < 1) return RF_E_ARG;
+    if (prec != RF_FP32 && prec != RF_FP64) return RF_E_ARG;
+    if (reinterpret_cast<uintptr_t>(plan_dev) % 256) return RF_E_ARG;
+    const Layout L = obs_layout(nobs, nuniq);
+    const char *p = static_cast<const char *>(plan_dev);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const unsigned nb = (unsigned)((nobs + 255) / 256);
+    const int32_t *idx = reinterpret_cast<const int32_t *>(p + L.off_idx);
+    const double *w = reinterpret_cast<const double *>(p + L.off_w);
+    const ObsPlanHeader *hd = static_cast<const ObsPlanHeader *>(plan_dev);
+    if (prec == RF_FP32)
+        k_obs_innov<float><<<nb, 256, 0, st>>>(hd, idx, w, (const float *)field, (const float *)yobs,
+                                               (const float *)rinv, (float)scale, (float *)d, (float *)rd, nobs,
+                                               nuniq, npts);
+    else
+        k_obs_innov<double><<<nb, 256, 0, st>>>(hd, idx, w, (const double *)field, (const double *)yobs,
+                                                (const double *)rinv, scale, (double *)d, (double *)rd, nobs,
+                                                nuniq, npts);
     return hipGetLastError() == hipSuccess ? RF_OK : RF_E_HIP;
 }

@@ -107,6 +107,10 @@ def lib() -> ctypes.CDLL:
         L.rf_cg_step.argtypes = [I, L64, P, P, P, P, P, P, P]
         L.rf_cg_dir.restype = I
         L.rf_cg_dir.argtypes = [I, L64, P, P, P, P]
+        L.rf_axpy.restype = I
+        L.rf_axpy.argtypes = [I, L64, ctypes.c_double, P, P, P]
+        L.rf_obs_innovation.restype = I
+        L.rf_obs_innovation.argtypes = [P, I, I, ctypes.c_int64, I, P, P, P, ctypes.c_double, P, P, P]
         L.rf_strerror.restype = ctypes.c_char_p
         L.rf_strerror.argtypes = [I]
         _lib = L
@@ -259,6 +263,12 @@ def rf_obs_adjoint(plan_dev, nobs, nuniq, npts, prec, obs, field, stream=None):
                                 _stream(stream)), "rf_obs_adjoint")
 
 
+def rf_obs_innovation(plan_dev, nobs, nuniq, npts, prec, field, yobs, rinv, scale, d, rd, stream=None):
+    _check(lib().rf_obs_innovation(_ptr(plan_dev), int(nobs), int(nuniq), int(npts), int(prec), _ptr(field),
+                                   _ptr(yobs), _ptr(rinv), float(scale), _ptr(d), _ptr(rd), _stream(stream)),
+           "rf_obs_innovation")
+
+
 def rf_cg_work_bytes() -> int:
     return lib().rf_cg_work_bytes()
 
@@ -280,3 +290,7 @@ def rf_cg_step(prec, n, p, q, v, r, work, s, stream=None):
 
 def rf_cg_dir(prec, n, r, p, s, stream=None):
     _check(lib().rf_cg_dir(int(prec), int(n), _ptr(r), _ptr(p), _ptr(s), _stream(stream)), "rf_cg_dir")
+
+
+def rf_axpy(prec, n, a, x, y, stream=None):
+    _check(lib().rf_axpy(int(prec), int(n), float(a), _ptr(x), _ptr(y), _stream(stream)), "rf_axpy")

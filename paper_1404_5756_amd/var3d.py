@@ -8,8 +8,9 @@ factored as B = V V^T.  With the control variable v (increment = V v) the cost i
     J(v) = 1/2 v.v + 1/2 (H V v - y).R^-1.(H V v - y),   grad J = v + V^T H^T R^-1 (H V v - y)
 and CG solves (I + V^T H^T R^-1 H V) v = V^T H^T R^-1 y, the same minimiser.
 Here V = V_H = G_y G_x per level.  Every iteration calls V and V^T once; both,
-H, H^T and the CG vector steps (deterministic FP64 dot products, scalars kept
-on the device) are librf3 calls.  torch only holds the vectors.
+H, H^T, the weighted innovation R^-1 (H V v - y), the gradient's sum and the CG
+vector steps (deterministic FP64 dot products, scalars kept on the device) are
+librf3 calls.  torch only holds the vectors.
 """
 from __future__ import annotations
 
@@ -93,21 +94,35 @@ class Var3D:
             rf3.rf_dot(self.prec, a.numel(), a, b, self.work, self.s, 3 + k)
         return self.s[3:3 + len(pairs)].tolist()
 
+    def _innov(self, field, yobs, scale, d=None):
+        """rd = scale * R^-1 (H field - yobs) in observation space (librf3); None drops a term."""
+        o = self.obs
+        rd = torch.empty(o.nobs, dtype=self.y.dtype, device=self.y.device)
+        if torch.is_tensor(self.rinv):
+            rinv, sc = self.rinv.to(self.y.dtype).contiguous(), scale
+        else:
+            rinv, sc = None, scale * float(self.rinv)
+        rf3.rf_obs_innovation(o.plan, o.nobs, o.nuniq, o.npts, self.prec, field, yobs, rinv, sc, d, rd)
+        return rd
+
     def cost_grad(self, v):
-        d = self.obs.apply(self.op.apply(v)) - self.y
-        rd = self.rinv * d
+        d = torch.empty_like(self.y)
+        rd = self._innov(self.op.apply(v), self.y, 1.0, d=d)
         vv, drd = self._dots([(v, v), (d, rd)])
         J = 0.5 * vv + 0.5 * drd
-        g = v + self.op.adjoint(self.obs.adjoint(rd))
+        g = self.op.adjoint(self.obs.adjoint(rd))
+        rf3.rf_axpy(self.prec, g.numel(), 1.0, v, g)   # g = v + V^T H^T R^-1 (H V v - y)
         return J, g
 
     def _vthv(self, p):
         """V^T H^T R^-1 H V p."""
-        return self.op.adjoint(self.obs.adjoint(self.rinv * self.obs.apply(self.op.apply(p))))
+        return self.op.adjoint(self.obs.adjoint(self._innov(self.op.apply(p), None, 1.0)))
 
     def hess(self, p):
         """(I + V^T H^T R^-1 H V) p."""
-        return p + self._vthv(p)
+        w = self._vthv(p)
+        rf3.rf_axpy(self.prec, w.numel(), 1.0, p, w)
+        return w
 
     def cg(self, iters, callback=None, track_cost=True):
         """CG from v = 0 on the normal equations; returns v and J after every iteration
@@ -115,7 +130,7 @@ class Var3D:
         scalars stay on the device: no host round trip inside the loop unless J is tracked."""
         n = self.obs.npts
         v = torch.zeros(self.obs.shape, dtype=self.y.dtype, device=self.y.device)
-        r = self.op.adjoint(self.obs.adjoint(self.rinv * self.y))
+        r = self.op.adjoint(self.obs.adjoint(self._innov(None, self.y, -1.0)))   # V^T H^T R^-1 y
         p = r.clone()
         q = torch.empty_like(p)
         rf3.rf_dot(self.prec, n, r, r, self.work, self.s, rf3.RF_CG_RR)

@@ -115,3 +115,16 @@ def test_coeffs_argument_errors(rf3):
     assert L.rf_coeffs(gp, FAKE, FAKE, FAKE, FAKE + 16, None) == rf3.RF_E_ARG
     bad = rf3.make_grid(64, 32, 4, n_img=100)
     assert L.rf_coeffs(ctypes.byref(bad), FAKE, FAKE, FAKE, FAKE, None) == rf3.RF_E_SHAPE
+
+
+def test_harness_argument_errors(rf3):
+    L = rf3.lib()
+    # null plan / output, bad precision: refused before any launch
+    assert L.rf_obs_innovation(None, 10, 10, 100, rf3.RF_FP32, None, None, None, 1.0, None, None, None) == rf3.RF_E_ARG
+    assert L.rf_obs_innovation(ctypes.c_void_p(1 << 40), 10, 10, 100, 7, None, None, None, 1.0, None,
+                               ctypes.c_void_p(1 << 40), None) == rf3.RF_E_ARG
+    assert L.rf_obs_innovation(ctypes.c_void_p((1 << 40) + 16), 10, 10, 100, rf3.RF_FP32, None, None, None, 1.0,
+                               None, ctypes.c_void_p(1 << 40), None) == rf3.RF_E_ARG   # misaligned plan
+    assert L.rf_axpy(rf3.RF_FP32, 0, 1.0, ctypes.c_void_p(1 << 40), ctypes.c_void_p(1 << 40), None) == rf3.RF_E_ARG
+    assert L.rf_axpy(rf3.RF_FP32, 10, 1.0, None, ctypes.c_void_p(1 << 40), None) == rf3.RF_E_ARG
+    assert L.rf_axpy(5, 10, 1.0, ctypes.c_void_p(1 << 40), ctypes.c_void_p(1 << 40), None) == rf3.RF_E_ARG

@@ -45,6 +45,37 @@ def test_obs_operator_matches_reference(grid, dtype):
     assert rel(gt, ov.obs_adjoint(d, idx, wt, f.size)) < tol
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_obs_innovation_matches_reference(grid, dtype):
+    """rd = scale * rinv o (H f - y): every combination of missing terms, per-observation
+    and unit weights, against the reference H."""
+    from paper_1404_5756_amd import rf3
+    w, op, lev, xs, ys = grid
+    obs = Observations(op, lev, xs, ys)
+    idx, wt = ov.obs_weights(w.nx, w.ny, lev, xs, ys)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((w.nlev, w.ny, w.nx))
+    y = rng.standard_normal(len(lev))
+    ri = rng.uniform(0.5, 4.0, len(lev))
+    hf = ov.obs_apply(f, idx, wt)
+    prec = rf3.RF_FP64 if dtype == torch.float64 else rf3.RF_FP32
+    tol = 1e-13 if dtype == torch.float64 else 1e-6
+    fd, yd, rid = (torch.from_numpy(a).to(DEV, dtype) for a in (f, y, ri))
+    for field, yy, rinv, scale in ((fd, yd, rid, 1.0), (fd, None, rid, 1.0), (None, yd, rid, -1.0),
+                                   (fd, yd, None, 2.5), (None, yd, None, -4.0)):
+        d = torch.full((len(lev),), float("nan"), dtype=dtype, device=DEV)
+        rd = torch.empty_like(d)
+        rf3.rf_obs_innovation(obs.plan, obs.nobs, obs.nuniq, obs.npts, prec, field, yy, rinv, scale, d, rd)
+        ref_d = (hf if field is not None else 0.0) - (y if yy is not None else 0.0)
+        ref_rd = scale * (ri if rinv is not None else 1.0) * ref_d
+        assert rel(d.double().cpu().numpy(), ref_d) < tol
+        assert rel(rd.double().cpu().numpy(), ref_rd) < tol
+    # d not stored
+    rd = torch.empty(len(lev), dtype=dtype, device=DEV)
+    rf3.rf_obs_innovation(obs.plan, obs.nobs, obs.nuniq, obs.npts, prec, fd, yd, None, 1.0, None, rd)
+    assert rel(rd.double().cpu().numpy(), hf - y) < tol
+
+
 def test_obs_adjoint_is_deterministic(grid):
     w, op, lev, xs, ys = grid
     obs = Observations(op, lev, xs, ys)
@@ -152,3 +183,8 @@ def test_cg_vector_kernels(dtype):
     rf3.rf_cg_dir(prec, n, r, p, s)
     assert rel(p.double().cpu().numpy(), rn + b * P) < tol
     assert float(s[rf3.RF_CG_RR]) == float(s[rf3.RF_CG_RR_NEW])
+    # y += a x
+    x, y = (torch.randn(n, generator=gen, device=DEV, dtype=dtype) for _ in range(2))
+    X, Y = (t.double().cpu().numpy() for t in (x, y))
+    rf3.rf_axpy(prec, n, -0.75, x, y)
+    assert rel(y.double().cpu().numpy(), Y - 0.75 * X) < tol

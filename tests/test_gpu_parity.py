@@ -49,6 +49,14 @@ CASES = [
     (10, 720, 150, 3, 0.3, 4, "fit", False, False, (2.0, 12.0)),
     (11, 801, 70, 3, 0.3, 4, "fit", False, False, (1.5, 12.0)),
     (12, 20, 2100, 1, 0.3, 4, "fit", False, False, (1.5, 12.0)),
+    # longest tiled lines (x: 2112 = 64 x 33, y: 1024 = 16 x 64) and one point past
+    # them (the line-sequential kernels take over for that direction)
+    (13, 18, 2112, 1, 0.3, 4, "fit", False, False, (1.5, 12.0)),
+    (14, 18, 2113, 1, 0.3, 4, "fit", False, False, (1.5, 12.0)),
+    (15, 1024, 40, 2, 0.3, 4, "fit", False, False, (1.5, 12.0)),
+    (16, 1025, 40, 2, 0.3, 4, "fit", False, False, (1.5, 12.0)),
+    # degenerate: all land (the output is zero)
+    (17, 50, 60, 2, 1.0, 2, "fit", False, False, (1.5, 8.0)),
 ]
 
 
@@ -162,6 +170,33 @@ def test_coast_codes_match_oracle_segments(case, orc):
                     bres[e] = 1
                 exp |= fres << 1 | bres << 2
                 assert np.array_equal(cl[k], exp), (d, l, k)
+
+
+@pytest.mark.parametrize("n_img", [0, 3])
+def test_single_sea_point_and_one_point_segments(orc, n_img):
+    """One isolated sea point, and rows/columns of alternating land and sea (every
+    segment one point long, or n_img imaginary points around it)."""
+    ny, nx = 33, 70
+    mask = np.zeros((1, ny, nx), np.uint8)
+    mask[0, 16, 35] = 1
+    mask[0, 3, ::2] = 1
+    mask[0, ::2, 5] = 1
+    rng = np.random.default_rng(17)
+    sx = rng.uniform(1.5, 9.0, (1, ny, nx))
+    sy = rng.uniform(1.5, 9.0, (1, ny, nx))
+    P = orc.Problem(mask, sx, sy, n_img=n_img, qmode=orc.QMODES["fit"], k1=5)
+    op = HorizontalCovariance(mask, sx, sy, 2, n_img=n_img, qmode="fit", k1=5)
+    x = rng.standard_normal((1, 2, ny, nx))
+    for out, ref in ((op.apply(torch.from_numpy(x).cuda()), P.rf3(x)),
+                     (op.adjoint(torch.from_numpy(x).cuda()), P.rf3_adjoint(x))):
+        assert rel(out.cpu().numpy(), ref) <= TOL64
+    x32 = x.astype(np.float32)
+    out = op.apply(torch.from_numpy(x32).cuda()).cpu().numpy()
+    assert rel(out, P.rf3(x32.astype(np.float64))) <= TOL32
+    # the isolated point's output is its input times beta_x * beta_y (a one-point segment
+    # with n_img = 0); with imaginary points around it the value differs
+    if n_img == 0:
+        assert out[0, 0, 16, 35] != 0
 
 
 def test_invalid_sigma_is_reported():

@@ -20,7 +20,7 @@
  *     every row and then on every column (Sec. 3, separability).
  *   - Adjoint: the transpose of the composed sweeps (derived, see below).
  *
- * Readings of points the paper leaves open (all listed in the design doc):
+ * Readings of points the paper leaves open:
  *   - coasts: each maximal run of sea points along a line is extended by
  *     up to n_img "imaginary sea points" taken from the adjacent land points;
  *     a land point goes to the nearer run (ties: the lower-index run).  The

@@ -50,7 +50,7 @@ typedef enum {
     RF_E_SHAPE = -2,        /* grid sizes out of range or inconsistent with the coefficient block */
     RF_E_SIGMA = -3,        /* sigma <= 0, NaN or Inf at a sea or imaginary point */
     RF_E_HIP = -4,          /* a HIP runtime call failed */
-    RF_E_UNSUPPORTED = -5   /* valid request this build does not handle */
+    RF_E_UNSUPPORTED = -5   /* valid request the library does not handle */
 } rf_status;
 
 typedef enum { RF_FP32 = 0, RF_FP64 = 1 } rf_prec;

@@ -167,7 +167,7 @@ extern "C" const char *rf_strerror(int status)
     case RF_E_SHAPE: return "invalid grid or level/field count";
     case RF_E_SIGMA: return "sigma not positive and finite at a sea or imaginary point";
     case RF_E_HIP: return "HIP runtime error";
-    case RF_E_UNSUPPORTED: return "request not supported by this build";
+    case RF_E_UNSUPPORTED: return "request not supported by the library";
     default: return "unknown status";
     }
 }

@@ -80,8 +80,9 @@ static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void
         if (e != hipErrorNotSupported) return e;
     }
     if (tiled2d && dir == 1 && h.ly) {
-        hipError_t e = fast_rf3_y(in, out, tab<float4>(coef, h.off_f32[1]), tab<uint64_t>(coef, h.off_lmy),
-                                  tab<float>(coef, h.off_phiy), h.ly, g->nx, g->ny, nplanes, adj, st);
+        hipError_t e = fast_rf3_y(in, out, tab<float4>(coef, h.off_f32[1]), tab<float>(coef, h.off_ky),
+                                  tab<uint64_t>(coef, h.off_lmy), tab<float>(coef, h.off_phiy), h.ly, g->nx, g->ny,
+                                  nplanes, adj, st);
         if (e != hipErrorNotSupported) return e;
     }
     const LineGeom G = geom(g, dir, nlev, nfields);

@@ -110,6 +110,7 @@ int build(const rf_batch_item *items, int32_t n, const rf_batch_tuning *tuning, 
             continue;
         }
         for (int d = 0; d < 2; ++d) e.T[d] = at<const float4>(it.coef, h.off_f32[d]);
+        e.KY = at<const float>(it.coef, h.off_ky);
         e.LM[0] = at<const uint64_t>(it.coef, h.off_lmx);
         e.LM[1] = at<const uint64_t>(it.coef, h.off_lmy);
         e.PHI[0] = at<const float>(it.coef, h.off_phix);

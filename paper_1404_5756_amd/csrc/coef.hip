@@ -280,6 +280,8 @@ BlockHeader layout(const rf_grid *g)
         off = align256(off + (size_t)((g->nx + kYCols - 1) / kYCols) * 4 * kYWaves * kYCols * 12 * 4);
     h.off_phix = off;
     if (h.lx && g->mask_nlev == 1 && g->sigma_nlev == 1) off = align256(off + (size_t)g->ny * 4 * 64 * 12 * 4);
+    h.off_ky = off;
+    if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1) off = align256(off + (size_t)4 * plane * 3 * 4);
     h.total_bytes = off;
     return h;
 }
@@ -334,6 +336,9 @@ extern "C" int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *si
     if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1) {
         if (setup_phi_y((const float4 *)(blk + h.off_f32[1]), (const uint8_t *)(blk + h.off_code[1]),
                         (float *)(blk + h.off_phiy), g->nx, g->ny, h.ly, st) != hipSuccess)
+            return RF_E_HIP;
+        if (setup_ky_y((const float4 *)(blk + h.off_f32[1]), (const uint8_t *)(blk + h.off_code[1]),
+                       (float *)(blk + h.off_ky), g->nx, g->ny, h.ly, st) != hipSuccess)
             return RF_E_HIP;
     }
     int32_t err = 0;

@@ -10,7 +10,7 @@
 namespace rf {
 
 constexpr uint32_t kMagic = 0x52463321u;   // "RF3!"
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 
 // Per-point coast code bits (one byte per point and direction).
 enum : uint8_t {
@@ -51,6 +51,7 @@ struct BlockHeader {
     uint64_t off_lmy;         // uint64 [mask_nlev][nblk][3][lys]: bit j = column 64*blk + j, entry 8+r = row r
     uint64_t off_phiy;        // float [nblk][4][16][64][12]: y-chunk transfer matrices (2-D mask and sigma only)
     uint64_t off_phix;        // float [ny][4][64][12]: x-chunk transfer matrices (2-D mask and sigma only)
+    uint64_t off_ky;          // float [4][ny][nx][3]: y local-pass K vectors (2-D mask and sigma only)
 };
 static_assert(sizeof(BlockHeader) <= 256, "header must fit in 256 bytes");
 
@@ -90,6 +91,7 @@ struct BatchEntry {
     const float *in;
     float *out;
     const float4 *T[2];
+    const float *KY;
     const uint64_t *LM[2];
     const float *PHI[2];
     int32_t nx, ny, nplanes, pad;

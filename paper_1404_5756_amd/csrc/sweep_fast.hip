@@ -480,9 +480,11 @@ constexpr int kYWin = 3;
 // One unit: planes pl0 .. pl0 + P-1 of one column block, each lane one column
 // of each plane.  phi: [2][16][64 * 9] in LDS (filled by y_planes); bsh: LDS
 // array of [2][16][2][64 * 3] floats, used here as [2][16][P][64 * 3].
+// KY: the local passes' K vectors [4 kinds][ny][nx][3].
 template <int L, bool ADJ, int P>
-__device__ __forceinline__ void y_unit(const float *in, float *out, const float4 *T, const uint64_t *LM, int nx_,
-                                       int ny_, int blk, int pl0, float (*phi)[kYWaves][kYCols * 9], float *bsh_raw)
+__device__ __forceinline__ void y_unit(const float *in, float *out, const float4 *T, const float *KY,
+                                       const uint64_t *LM, int nx_, int ny_, int blk, int pl0,
+                                       float (*phi)[kYWaves][kYCols * 9], float *bsh_raw)
 {
     auto bsh = reinterpret_cast<float (*)[kYWaves][P][kYCols * 3]>(bsh_raw);
     constexpr int LB = (L + 7) / 8;   // 8-row mask blocks per chunk
@@ -491,9 +493,16 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
     const long plane = (long)nx_ * ny_;
     const int lys = lmy_stride(L);
     const uint64_t *lm = LM + (long)blk * 3 * lys + 8;   // entry r = row r
-    // columns past the grid: offsets beyond every buffer (loads read 0, stores are dropped)
-    const uint32_t cb = col < nx_ ? (uint32_t)col * 4u : 0x7fffffffu;
-    const uint32_t cbt = col < nx_ ? (uint32_t)col * 16u : 0x7fffffffu;
+    // byte offset of my column in the field; columns past the grid get 2^29, past
+    // every table (the y kernels need nx * ny < 2^27), so loads read 0 and stores
+    // are dropped.  The coefficient (16 B) and K (12 B) offsets are 4x and 3x this,
+    // formed inside each pass so that only this one stays live.
+    const uint32_t cb = col < nx_ ? (uint32_t)col * 4u : 0x20000000u;
+    auto col_off = [&](uint32_t mul) {
+        uint32_t o = cb * mul;
+        asm volatile("" : "+v"(o));
+        return o;
+    };
     const Rsrc rt = make_rsrc(T, (uint32_t)(plane * 16));
     {
         // opaque per unit: keeps the per-row offsets and conditions out of the
@@ -518,13 +527,56 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
                 roff = fresh_int(min(roff + rowb, last));
             }
         }
-        // one pass over the chunk for all P planes.  MODE 1: local (no output; the
-        // first pass also masks the input to sea points as the rows arrive),
-        // MODE 2: output into v; the last pass (descending) applies the output sea
-        // mask and stores each row as it is produced.
+        // local pass: the chunk's end state from a zero state is the dot product of
+        // its inputs with the K vectors of this sweep (resets are folded into K, the
+        // forward causal K also holds beta).  The first one masks the input to sea
+        // points as the rows arrive.
+        auto local = [&](St *x, auto DC) {
+            constexpr bool desc = decltype(DC)::value;
+            constexpr bool first = !desc;
+            const int kind = (ADJ ? 2 : 0) + (desc ? 1 : 0);
+            const Rsrc rk = make_rsrc(KY + (long)kind * plane * 3, (uint32_t)(plane * 12));
+            const uint64_t *sp = lm + 2 * lys + r0;
+            const int krow = nx * 12, klast = (ny - 1) * krow;
+            const uint32_t cbk = col_off(3);
+            int cur = fresh_int(r0 * krow);
+            auto kload = [&]() -> u32x3 {
+                const u32x3 z = __builtin_amdgcn_raw_buffer_load_b96(rk, cbk, min(cur, klast), 0);
+                cur = fresh_int(cur + krow);
+                return z;
+            };
+            u32x3 win[kYWin];
+#pragma unroll
+            for (int q = 0; q < kYWin; ++q) win[q] = kload();
+#pragma unroll
+            for (int b = 0; b < LB; ++b) {
+                u32x16 sm;
+                if (first) sm = sload16(sp + 8 * b);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int i = 8 * b + q;
+                    if (i >= L) continue;
+                    const u32x3 k = win[i % kYWin];
+                    if (i + kYWin < L) win[i % kYWin] = kload();
+                    const float k0 = __uint_as_float(k.x), k1 = __uint_as_float(k.y), k2 = __uint_as_float(k.z);
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        if (first) v[p][i] = zero_if(v[p][i], m64_of(sm, q));
+                        x[p].a = fmaf(k0, v[p][i], x[p].a);
+                        x[p].b = fmaf(k1, v[p][i], x[p].b);
+                        x[p].c = fmaf(k2, v[p][i], x[p].c);
+                    }
+                    mem_fence_compiler();   // keep the window's loads from being hoisted further
+                }
+            }
+        };
+        // rerun over the chunk for all P planes from the true incoming state, output
+        // into v; the last pass (descending) applies the output sea mask and stores
+        // each row as it is produced.
         auto pass = [&](St *x, auto DC, auto MC) {
             constexpr bool desc = decltype(DC)::value;
             constexpr int mode = decltype(MC)::value;
+            static_assert(mode == 2, "local passes use the K vectors");
             // ascending uses FRESET (forward: before the step) or BRESET (adjoint: after);
             // descending uses BRESET (forward) or FRESET (adjoint)
             const uint64_t *rp = lm + ((ADJ ? !desc : desc) ? lys : 0) + r0;
@@ -532,13 +584,14 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
             // byte offset of the next row to fetch, a chain through opaque values so
             // that the offsets are formed one at a time; clamped at the last row
             const int crow = nx * 16, clast = (ny - 1) * crow;
+            const uint32_t cbt = col_off(4);
             int cur = fresh_int((desc ? r0 + L - 1 : r0) * crow);
             auto cload = [&]() -> u32x4 {
                 const u32x4 z = __builtin_amdgcn_raw_buffer_load_b128(rt, cbt, min(cur, clast), 0);
                 cur = fresh_int(cur + (desc ? -crow : crow));
                 return z;
             };
-            constexpr bool first = !desc && mode == 1, last = desc && mode == 2;
+            constexpr bool last = desc;
             const int lim = ny * rowb;
             int soff = fresh_int((r0 + L - 1) * rowb);   // store offset of the current row (last pass)
             u32x4 win[kYWin];
@@ -549,7 +602,7 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
                 const int b = desc ? LB - 1 - bb : bb;
                 const u32x16 m = sload16(rp + 8 * b);
                 u32x16 sm;
-                if (first || last) sm = sload16(sp + 8 * b);
+                if (last) sm = sload16(sp + 8 * b);
 #pragma unroll
                 for (int qq = 0; qq < 8; ++qq) {
                     const int q = desc ? 7 - qq : qq;
@@ -563,14 +616,10 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
                     const uint64_t mm = m64_of(m, q);
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        if (first) {   // input only at sea points; forward: beta_i s_i for both passes
-                            v[p][i] = zero_if(v[p][i], m64_of(sm, q));
-                            if (!ADJ) v[p][i] = bt * v[p][i];
-                        }
                         float o;
-                        if (!ADJ) {
+                        if (!ADJ) {   // causal input beta_i s_i; the anti-causal one is prescaled
                             st_reset(x[p], mm);
-                            fwd_step(x[p], v[p][i], gm, c2, c3);
+                            fwd_step(x[p], desc ? v[p][i] : bt * v[p][i], gm, c2, c3);
                             o = x[p].a;
                         } else {
                             o = adj_step<mode == 2>(x[p], v[p][i], bt, gm, c2, c3);
@@ -598,7 +647,7 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
             St x[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) x[p] = St{0.f, 0.f, 0.f};
-            pass(x, DC, std::integral_constant<int, 1>{});
+            local(x, DC);
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 bsh[sw][w][p][lane * 3] = x[p].a;
@@ -637,8 +686,8 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
 // and a one-plane unit for an odd count, run first when single_first is set
 // (so that neighbouring workgroups do not reach their memory phases together).
 template <int L, bool ADJ>
-__device__ __forceinline__ void y_planes(const float *in, float *out, const float4 *T, const uint64_t *LM,
-                                         const float *PHI, int nx, int ny, int blk, int pa, int pb,
+__device__ __forceinline__ void y_planes(const float *in, float *out, const float4 *T, const float *KY,
+                                         const uint64_t *LM, const float *PHI, int nx, int ny, int blk, int pa, int pb,
                                          bool single_first, float (*phi)[kYWaves][kYCols * 9], float *bsh)
 {
     constexpr int PM = y_planes_per_lane(L);
@@ -653,21 +702,21 @@ __device__ __forceinline__ void y_planes(const float *in, float *out, const floa
     }
     __syncthreads();
     if (PM == 2 && single_first && ((pb - pa) & 1)) {
-        y_unit<L, ADJ, 1>(in, out, T, LM, nx, ny, blk, pa, phi, bsh);
+        y_unit<L, ADJ, 1>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
         ++pa;
         __syncthreads();   // bsh is rewritten by the next unit
     }
     for (; pa + PM <= pb; pa += PM) {
-        y_unit<L, ADJ, PM>(in, out, T, LM, nx, ny, blk, pa, phi, bsh);
+        y_unit<L, ADJ, PM>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
         __syncthreads();
     }
-    if (pa < pb) y_unit<L, ADJ, 1>(in, out, T, LM, nx, ny, blk, pa, phi, bsh);
+    if (pa < pb) y_unit<L, ADJ, 1>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
 }
 
 // Workgroup (column block, slot): slot j of S takes planes [j n / S, (j+1) n / S).
 template <int L, bool ADJ>
 __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float *out, const float4 *T,
-                                                         const uint64_t *__restrict__ LM,
+                                                         const float *KY, const uint64_t *__restrict__ LM,
                                                          const float *__restrict__ PHI, int nx, int ny,
                                                          int nplanes, int nblk, int nslot)
 {
@@ -678,7 +727,7 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float
     const int blk = (slot / nslot) * 8 + xcd, j = slot % nslot;
     if (blk >= nblk) return;
     const int pa = (int)((long)j * nplanes / nslot), pb = (int)((long)(j + 1) * nplanes / nslot);
-    y_planes<L, ADJ>(in, out, T, LM, PHI, nx, ny, blk, pa, pb, (j & 1) != 0, phi, bsh);
+    y_planes<L, ADJ>(in, out, T, KY, LM, PHI, nx, ny, blk, pa, pb, (j & 1) != 0, phi, bsh);
 }
 
 // Batched form: one workgroup per work unit {item, column block, first and end plane}.
@@ -692,7 +741,7 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_batch(const BatchEntry
     const int item = uni(up->item);
     if (item < 0) return;
     const BatchEntry *e = E + item;
-    y_planes<L, ADJ>(uni(src_out ? (const float *)e->out : e->in), uni(e->out), uni(e->T[1]), uni(e->LM[1]),
+    y_planes<L, ADJ>(uni(src_out ? (const float *)e->out : e->in), uni(e->out), uni(e->T[1]), uni(e->KY), uni(e->LM[1]),
                      uni(e->PHI[1]), uni(e->nx), uni(e->ny), uni(up->a), uni(up->b), uni(up->c), false, phi, bsh);
 }
 
@@ -763,6 +812,67 @@ __global__ void k_phi_y(const float4 *__restrict__ T, const uint8_t *__restrict_
     chunk_transfer(kind, L, cf, cd, dst);
 }
 
+// y kernel's local passes: K vectors.  The state a sweep leaves at the end of
+// chunk w, from a zero state, is sum_i K_i v_i over the chunk's rows, with K_i
+// the response of that end state to a unit input at row i: the state right
+// after row i's step, carried through the later steps of the chunk (resets
+// included: a reset after row i zeroes K_i).  Forward causal: the input is s
+// and the step injects (beta, beta, 0); forward anti-causal: the input is
+// beta u, injection (1, 1, 0); adjoint: injection (1 - gamma, -c2, -c3), then
+// the reset after the step.  Kinds and reset flags as in chunk_transfer; rows
+// past the grid reset and carry nothing.  KY[kind][r][col][3], FP64 from the
+// FP32 table; one thread per (column, chunk, kind).
+__global__ void k_kvec_y(const float4 *__restrict__ T, const uint8_t *__restrict__ code, float *__restrict__ KY,
+                         int nx, int ny, int L, int nblk)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nblk * kYCols * kYWaves * 4) return;
+    const int j = (int)(t % kYCols);
+    const int w = (int)((t / kYCols) % kYWaves);
+    const int kind = (int)((t / (kYCols * kYWaves)) % 4);
+    const int blk = (int)(t / (kYCols * kYWaves * 4));
+    const int col = blk * kYCols + j;
+    if (col >= nx) return;
+    const bool desc = kind & 1, adj = kind >= 2;
+    const uint8_t flag = kind == 0 ? CODE_FRESET : kind == 1 ? CODE_BRESET : kind == 2 ? CODE_BRESET : CODE_FRESET;
+    double P[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};   // steps after the current one, composed
+    for (int k = L - 1; k >= 0; --k) {             // sweep steps, last first
+        const int i = desc ? L - 1 - k : k;
+        const int r = w * L + i;
+        const bool in = r < ny;
+        const float4 c = in ? T[(long)r * nx + col] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const bool rs = in ? (code[(long)r * nx + col] & flag) != 0 : true;
+        const double bt = c.x, gm = c.y, c2 = c.z, c3 = c.w;
+        double u[3];
+        if (!adj) {
+            const double s = desc ? 1.0 : bt;
+            u[0] = s; u[1] = s; u[2] = 0.0;
+        } else {
+            u[0] = rs ? 0.0 : 1.0 - gm; u[1] = rs ? 0.0 : -c2; u[2] = rs ? 0.0 : -c3;
+        }
+        if (in) {
+            float *dst = KY + (((long)kind * ny + r) * nx + col) * 3;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) dst[e] = (float)(P[3 * e] * u[0] + P[3 * e + 1] * u[1] + P[3 * e + 2] * u[2]);
+        }
+        // P <- P * (this step's map with zero input); a reset makes it zero
+        double M[9];
+        if (rs) {
+            for (int e = 0; e < 9; ++e) M[e] = 0.0;
+        } else if (!adj) {   // (p, d1, d2) -> (p + t, t, d1), t = -gm p - c2 d1 - c3 d2
+            const double m[9] = {1 - gm, -c2, -c3, -gm, -c2, -c3, 0, 1, 0};
+            for (int e = 0; e < 9; ++e) M[e] = m[e];
+        } else {             // (a, b, c) -> (a - gm u, c - c2 u, -c3 u), u = a + b
+            const double m[9] = {1 - gm, -gm, 0, -c2, -c2, 1, -c3, -c3, 0};
+            for (int e = 0; e < 9; ++e) M[e] = m[e];
+        }
+        double N[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) N[3 * a + b] = P[3 * a] * M[b] + P[3 * a + 1] * M[3 + b] + P[3 * a + 2] * M[6 + b];
+        for (int e = 0; e < 9; ++e) P[e] = N[e];
+    }
+}
+
 // x kernel's chunks: PHI[row][kind][c][12], one thread per (row, kind, chunk)
 __global__ void k_phi_x(const float4 *__restrict__ T, const uint8_t *__restrict__ code, float *__restrict__ PHI,
                         int nx, int ny, int L)
@@ -831,8 +941,8 @@ static double y_range_cost(int n, int pm)
 }
 
 template <int L, bool ADJ>
-static hipError_t launch_y(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
-                           int nx, int ny, int nplanes, hipStream_t st)
+static hipError_t launch_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
+                           const float *PHI, int nx, int ny, int nplanes, hipStream_t st)
 {
     constexpr int PM = y_planes_per_lane(L);
     static_assert(PM == 1 || PM == 2, "planes per lane");
@@ -848,7 +958,7 @@ static hipError_t launch_y(const float *in, float *out, const float4 *T, const u
         if (best_cost < 0 || cost < best_cost - 1e-9) { best_cost = cost; best = sl; }
     }
     const unsigned nb = (unsigned)(nb8 * best);
-    k_rf3y<L, ADJ><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, nblk, best);
+    k_rf3y<L, ADJ><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nplanes, nblk, best);
     return hipGetLastError();
 }
 
@@ -858,8 +968,8 @@ static hipError_t launch_y(const float *in, float *out, const float4 *T, const u
                    : launch_x<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, st);
 #define RF_Y_CASE(Lv)                                                                                     \
     case Lv:                                                                                              \
-        return adj ? launch_y<Lv, true>(in, out, T, LM, PHI, nx, ny, nplanes, st)                         \
-                   : launch_y<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, st);
+        return adj ? launch_y<Lv, true>(in, out, T, KY, LM, PHI, nx, ny, nplanes, st)                     \
+                   : launch_y<Lv, false>(in, out, T, KY, LM, PHI, nx, ny, nplanes, st);
 
 hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int lx,
                       int nx, int ny, int nplanes, bool adj, hipStream_t st)
@@ -872,8 +982,8 @@ hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64
     }
 }
 
-hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int ly,
-                      int nx, int ny, int nplanes, bool adj, hipStream_t st)
+hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
+                      const float *PHI, int ly, int nx, int ny, int nplanes, bool adj, hipStream_t st)
 {
     // scalar row offsets into the coefficient table are 32-bit
     if ((long)nx * ny * 16 >= (1L << 31)) return hipErrorNotSupported;
@@ -924,6 +1034,14 @@ hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx,
 {
     const long n = (long)ny * 4 * 64;
     k_phi_x<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(T, code, PHI, nx, ny, lx);
+    return hipGetLastError();
+}
+
+hipError_t setup_ky_y(const float4 *T, const uint8_t *code, float *KY, int nx, int ny, int ly, hipStream_t st)
+{
+    const int nblk = (nx + kYCols - 1) / kYCols;
+    const long n = (long)nblk * kYCols * kYWaves * 4;
+    k_kvec_y<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(T, code, KY, nx, ny, ly, nblk);
     return hipGetLastError();
 }
 

@@ -29,8 +29,8 @@ namespace rf {
 // tiled FP32 kernels (sweep_fast.hip); hipErrorNotSupported when the tile size is not covered
 hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int lx,
                       int nx, int ny, int nplanes, bool adj, hipStream_t st);
-hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int ly,
-                      int nx, int ny, int nplanes, bool adj, hipStream_t st);
+hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
+                      const float *PHI, int ly, int nx, int ny, int nplanes, bool adj, hipStream_t st);
 // batched forms over a work list (all units of one launch share the tile size)
 hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int lx, bool adj, bool src_out,
                             hipStream_t st);
@@ -38,5 +38,6 @@ hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits,
                             hipStream_t st);
 int x_groups(int ny, int nplanes, int gmax);
 hipError_t setup_phi_y(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int ly, hipStream_t st);
+hipError_t setup_ky_y(const float4 *T, const uint8_t *code, float *KY, int nx, int ny, int ly, hipStream_t st);
 hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int lx, hipStream_t st);
 }  // namespace rf

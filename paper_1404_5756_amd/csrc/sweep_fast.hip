@@ -149,6 +149,12 @@ typedef __amdgpu_buffer_rsrc_t Rsrc;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 
+// cache policies of the field accesses (data read or written once): the
+// non-temporal hint, so that streaming a field does not evict the coefficient
+// tables the sweeps re-read from L2.  The x kernel keeps its coefficients in
+// registers and reads its lines with the default policy.
+constexpr int kStreamLoadY = 2, kStreamStoreY = 2, kStreamStoreX = 2;
+
 // raw buffer over nbytes at p: loads past the end read 0, stores past it are dropped
 __device__ __forceinline__ Rsrc make_rsrc(const void *p, uint32_t nbytes)
 {
@@ -424,7 +430,7 @@ __device__ __forceinline__ void x_rows(const float *in, float *out, const float4
                 w.y = __float_as_uint(q.y);
                 w.z = __float_as_uint(q.z);
                 w.w = __float_as_uint(q.w);
-                __builtin_amdgcn_raw_buffer_store_b128(w, ro, (4 * lane + 256 * it) * 4, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b128(w, ro, (4 * lane + 256 * it) * 4, 0, kStreamStoreX);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -523,7 +529,7 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
             for (int i = 0; i < L; ++i) {
 #pragma unroll
                 for (int p = 0; p < P; ++p)
-                    v[p][i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ri[p], cb, roff, 0));
+                    v[p][i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ri[p], cb, roff, kStreamLoadY));
                 roff = fresh_int(min(roff + rowb, last));
             }
         }
@@ -632,7 +638,7 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
                         if (soff < lim) {   // rows past the grid are not stored
 #pragma unroll
                             for (int p = 0; p < P; ++p)
-                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[p][i]), ro[p], cb, soff, 0);
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[p][i]), ro[p], cb, soff, kStreamStoreY);
                         }
                         soff = fresh_int(soff - rowb);
                     }

@@ -176,20 +176,24 @@ def main():
     value = pts / (ms_step * 1e-3) / 1e9
     log(f"step (fwd+adj): {ms_step:.3f} ms -> {value:.1f} Gpoints/s")
 
-    # ---- per-kernel times (each call of rf3_apply_dir is one kernel launch)
+    # ---- per-kernel times, in the step's own order and data flow (rf3_apply_xy is
+    # x: x -> out then y: out -> out; rf3_adjoint_xy is y then x), one event between
+    # launches; each call of rf3_apply_dir is one kernel launch
     reps = max(5, args.steps)
-    kern = {}
-    for name, d, adj in (("x_fwd", 0, False), ("y_fwd", 1, False), ("y_adj", 1, True), ("x_adj", 0, True)):
-        dst = out_f if not adj else out_a
-        op.apply_dir(x, d, adj, out=dst)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
-            op.apply_dir(x, d, adj, out=dst)
-        b.record(stream)
-        torch.cuda.synchronize()
-        kern[name] = a.elapsed_time(b) / reps
+    seq = (("x_fwd", 0, False, x, out_f), ("y_fwd", 1, False, out_f, out_f),
+           ("y_adj", 1, True, x, out_a), ("x_adj", 0, True, out_a, out_a))
+    for name, d, adj, src, dst in seq:
+        op.apply_dir(src, d, adj, out=dst)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(seq) + 1)] for _ in range(reps)]
+    for r in range(reps):
+        evs[r][0].record(stream)
+        for k, (name, d, adj, src, dst) in enumerate(seq):
+            op.apply_dir(src, d, adj, out=dst)
+            evs[r][k + 1].record(stream)
+    torch.cuda.synchronize()
+    kern = {name: sum(evs[r][k].elapsed_time(evs[r][k + 1]) for r in range(reps)) / reps
+            for k, (name, *_rest) in enumerate(seq)}
     log("kernel ms: " + ", ".join(f"{k} {v:.3f}" for k, v in kern.items()))
     dom = max(kern, key=kern.get)
     bytes_per_launch = 8.0 * pts        # FP32 read + write of every point once

@@ -10,6 +10,13 @@ namespace {
 
 constexpr int kCgBlocks = 1024, kCgThreads = 256;
 
+// vectors are streamed once per kernel: non-temporal accesses, so that they do
+// not evict the covariance operator's coefficient tables from L2
+template <class T>
+__device__ __forceinline__ T ld(const T *p) { return __builtin_nontemporal_load(p); }
+template <class T>
+__device__ __forceinline__ void st(T *p, T v) { __builtin_nontemporal_store(v, p); }
+
 __device__ double block_sum(double v, double *sh)
 {
     const int t = threadIdx.x;
@@ -30,7 +37,7 @@ __global__ __launch_bounds__(kCgThreads) void k_dot(const T *__restrict__ a, con
     __shared__ double sh[kCgThreads];
     double acc = 0.0;
     for (long i = (long)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += (long)kCgBlocks * kCgThreads)
-        acc += (double)a[i] * (double)b[i];
+        acc += (double)ld(a + i) * (double)ld(b + i);
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
@@ -43,8 +50,8 @@ __global__ __launch_bounds__(kCgThreads) void k_q_dot(const T *__restrict__ p, c
     __shared__ double sh[kCgThreads];
     double acc = 0.0;
     for (long i = (long)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += (long)kCgBlocks * kCgThreads) {
-        const T pi = p[i], qi = pi + w[i];
-        q[i] = qi;
+        const T pi = ld(p + i), qi = pi + ld(w + i);
+        st(q + i, qi);
         acc += (double)pi * (double)qi;
     }
     const double s = block_sum(acc, sh);
@@ -63,9 +70,9 @@ __global__ __launch_bounds__(kCgThreads) void k_step(const T *__restrict__ p, co
     const T a = pq > 0.0 ? (T)(s[RF_CG_RR] / pq) : (T)0;
     double acc = 0.0;
     for (long i = (long)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += (long)kCgBlocks * kCgThreads) {
-        v[i] += a * p[i];
-        const T ri = r[i] - a * q[i];
-        r[i] = ri;
+        st(v + i, ld(v + i) + a * ld(p + i));
+        const T ri = ld(r + i) - a * ld(q + i);
+        st(r + i, ri);
         acc += (double)ri * (double)ri;
     }
     const double sum = block_sum(acc, sh);
@@ -80,7 +87,7 @@ __global__ __launch_bounds__(kCgThreads) void k_dir(const T *__restrict__ r, T *
     const double rr = s[RF_CG_RR];
     const T b = rr > 0.0 ? (T)(s[RF_CG_RR_NEW] / rr) : (T)0;
     for (long i = (long)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += (long)kCgBlocks * kCgThreads)
-        p[i] = r[i] + b * p[i];
+        st(p + i, ld(r + i) + b * ld(p + i));
 }
 
 // s[slot] = sum of the partials in a fixed order
@@ -101,7 +108,7 @@ template <class T>
 __global__ __launch_bounds__(kCgThreads) void k_axpy(T a, const T *__restrict__ x, T *__restrict__ y, long n)
 {
     for (long i = (long)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += (long)kCgBlocks * kCgThreads)
-        y[i] += a * x[i];
+        st(y + i, ld(y + i) + a * ld(x + i));
 }
 
 bool args_ok(int prec, long n, const void *a, const void *b)

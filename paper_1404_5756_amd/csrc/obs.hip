@@ -141,7 +141,8 @@ __global__ void k_obs_innov(const ObsPlanHeader *__restrict__ hd, const int32_t 
 template <class T>
 __global__ void k_fill(T *__restrict__ f, long n)
 {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) f[i] = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store((T)0, f + i);   // streamed once: keep L2 for the tables
 }
 
 template <class T>

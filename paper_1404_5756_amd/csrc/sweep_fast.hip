@@ -138,10 +138,10 @@ __device__ __forceinline__ void mat_acc(const float *A, const St &x, St &y)
 // x direction: one wave per line (a row of one plane); lane c owns points
 // [c*L, c*L + L) with L odd.  All waves of a workgroup work on lines of the
 // same row, which share its coefficients, lane masks and scan matrices.
-// Loads go straight into the chunk layout (range-checked buffer loads; the
-// next line is prefetched into registers while the current one is filtered).
-// Results go through LDS so that the stores are coalesced; the odd L keeps the
-// chunk-major LDS writes free of bank conflicts.
+// Lines are loaded and stored in coalesced dwordx4 rounds (range-checked
+// buffer accesses) and pass through LDS between that order and the chunk
+// layout; the odd L keeps the chunk-major LDS accesses free of bank conflicts.
+// The next line is in flight in registers while the current one is filtered.
 // ======================================================================
 constexpr int kXWaves = 4;
 
@@ -151,37 +151,15 @@ typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 
 // cache policies of the field accesses (data read or written once): the
 // non-temporal hint, so that streaming a field does not evict the coefficient
-// tables the sweeps re-read from L2.  The x kernel keeps its coefficients in
-// registers and reads its lines with the default policy.
-constexpr int kStreamLoadY = 2, kStreamStoreY = 2, kStreamStoreX = 2;
+// tables the sweeps re-read from L2 (the x kernel's coalesced line loads and
+// stores too: it keeps its own coefficients in registers, but the y kernel
+// after it needs L2 for its tables).
+constexpr int kStreamLoadY = 2, kStreamStoreY = 2, kStreamLoadX = 2, kStreamStoreX = 2;
 
 // raw buffer over nbytes at p: loads past the end read 0, stores past it are dropped
 __device__ __forceinline__ Rsrc make_rsrc(const void *p, uint32_t nbytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)nbytes, 0x00020000);
-}
-
-// L consecutive floats at byte offset off into v (dwordx4 groups, then the rest)
-template <int L>
-__device__ __forceinline__ void chunk_load(Rsrc r, int off, float *v)
-{
-#pragma unroll
-    for (int j = 0; j + 4 <= L; j += 4) {
-        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off + 4 * j, 0, 0);
-        v[j] = __uint_as_float(a.x);
-        v[j + 1] = __uint_as_float(a.y);
-        v[j + 2] = __uint_as_float(a.z);
-        v[j + 3] = __uint_as_float(a.w);
-    }
-    constexpr int j = L & ~3, rem = L & 3;
-    if (rem == 3) {
-        const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, off + 4 * j, 0, 0);
-        v[j] = __uint_as_float(a.x);
-        v[j + 1] = __uint_as_float(a.y);
-        v[j + 2] = __uint_as_float(a.z);
-    }
-    if (rem == 1) v[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off + 4 * j, 0, 0));
-    static_assert(rem != 2, "L is odd");
 }
 
 template <int L, bool ADJ>
@@ -392,13 +370,27 @@ __device__ __forceinline__ void x_rows(const float *in, float *out, const float4
     const int lstep = groups * kXWaves;
     const int nst = (nx + 255) / 256;   // dwordx4 store rounds per line
     int ln = grp + groups * wave;
-    float v[L], vn[L];   // the current line, and the next one in flight
-    if (ln < nplanes) chunk_load<L>(make_rsrc(in + (long)ln * plane + (long)row * nx, line_bytes), x0 * 4, vn);
+    // lines arrive in coalesced dwordx4 rounds (lane l: floats 4l .. 4l+3 of each
+    // 256) with the non-temporal hint, and go into chunk layout through this
+    // wave's LDS staging area; the next line is in flight while one is filtered
+    constexpr int NR = (L + 3) / 4;
+    float v[L];
+    u32x4 q[NR];
+    auto line_load = [&](int l) {
+        const Rsrc r = make_rsrc(in + (long)l * plane + (long)row * nx, line_bytes);
+#pragma unroll
+        for (int it = 0; it < NR; ++it)
+            q[it] = __builtin_amdgcn_raw_buffer_load_b128(r, (4 * lane + 256 * it) * 4, 0, kStreamLoadX);
+    };
+    if (ln < nplanes) line_load(ln);
     for (; ln < nplanes; ln += lstep) {
 #pragma unroll
-        for (int i = 0; i < L; ++i) v[i] = vn[i];
-        if (ln + lstep < nplanes)
-            chunk_load<L>(make_rsrc(in + (long)(ln + lstep) * plane + (long)row * nx, line_bytes), x0 * 4, vn);
+        for (int it = 0; it < NR; ++it) *reinterpret_cast<u32x4 *>(stg + 4 * lane + 256 * it) = q[it];
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS writes done
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < L; ++i) v[i] = stg[x0 + i];
+        if (ln + lstep < nplanes) line_load(ln + lstep);
         {
             mask_ptr sp = R.lm + 2 * XRow<L, ADJ>::LP + fresh_int(0);
 #pragma unroll

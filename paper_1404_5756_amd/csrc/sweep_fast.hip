@@ -473,7 +473,7 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x_batch(
 // offsets, clamped to the grid: rows past the end are outside every segment
 // (their input is masked off and they are never stored).
 // ======================================================================
-constexpr int kYWin = 3;
+constexpr int kYWin = 2;
 
 // One unit: planes pl0 .. pl0 + P-1 of one column block, each lane one column
 // of each plane.  phi: [2][16][64 * 9] in LDS (filled by y_planes); bsh: LDS

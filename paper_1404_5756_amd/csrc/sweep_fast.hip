@@ -894,12 +894,29 @@ __global__ void k_phi_x(const float4 *__restrict__ T, const uint8_t *__restrict_
 }
 
 // ---------------------------------------------------------------- dispatch
-// groups per row for the x kernel: enough workgroups to cover the chip several
-// times, at least two lines per wave, at most gmax
+// compute units of the current device (cached per device)
+static int cu_count()
+{
+    static int cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
+// groups per row for the x kernel (workgroups sharing one row's planes): more
+// only while the rows alone give fewer than two workgroups per CU (a
+// workgroup's setup, the row's coefficients and scan matrices, is paid once
+// per group), at least two lines per wave, at most gmax
 int x_groups(int ny, int nplanes, int gmax)
 {
+    const long target = 2L * cu_count();
     int groups = 1;
-    while (groups * 2 <= gmax && (long)((ny + 7) / 8) * 8 * groups < 2048 && groups * kXWaves * 2 <= nplanes)
+    while (groups * 2 <= gmax && (long)((ny + 7) / 8) * 8 * groups < target && groups * kXWaves * 2 <= nplanes)
         groups *= 2;
     return groups;
 }
@@ -914,19 +931,6 @@ static hipError_t launch_x(const float *in, float *out, const float4 *T, const u
     return hipGetLastError();
 }
 
-// compute units of the current device (cached per device)
-static int cu_count()
-{
-    static int cache[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (!cache[dev]) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-        cache[dev] = n;
-    }
-    return cache[dev];
-}
 
 // time of a one-plane y unit relative to a two-plane one with every CU busy
 // (measured on 1440 x 720 grids: the memory phases dominate both)

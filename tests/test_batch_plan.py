@@ -21,9 +21,10 @@ def _item(k, nx, ny, nlev, nfields=1, mask_nlev=1, sigma_nlev=1, in_place=False)
     return (g, coef, inp, out, nfields)
 
 
-def _x_groups(ny, nplanes):
+def _x_groups(ny, nplanes, gmax=8, cus=256):
+    """Workgroups per x row (the library's rule; without a GPU the library assumes 256 CUs)."""
     groups = 1
-    while groups < 8 and ((ny + 7) // 8) * 8 * groups < 2048 and groups * 4 * 2 <= nplanes:
+    while groups * 2 <= gmax and ((ny + 7) // 8) * 8 * groups < 2 * cus and groups * 4 * 2 <= nplanes:
         groups *= 2
     return groups
 
@@ -126,9 +127,7 @@ def test_tuning_shapes_the_work_list():
         units = [struct.unpack_from("<iiii", buf, off_u + 16 * k) for k in range(n_units)]
         real = [u for u in units if u[0] >= 0]
         cap = 1 << (xg.bit_length() - 1)     # the largest power of two not above x_groups_max
-        groups = 1
-        while groups * 2 <= cap and ((200 + 7) // 8) * 8 * groups < 2048 and groups * 4 * 2 <= nplanes:
-            groups *= 2
+        groups = _x_groups(200, nplanes, cap)
         xu = [u for u in real[:200 * groups]]
         assert sorted((u[1], u[2]) for u in xu) == [(r, q) for r in range(200) for q in range(groups)]
         yu = real[200 * groups:]

@@ -232,9 +232,11 @@ int rf_obs_innovation(const void *plan_dev, int32_t nobs, int32_t nuniq, int64_t
  * (caller-owned, device, rf_cg_work_bytes() bytes), then one block adds them
  * in a fixed order.  Vectors are n elements of `prec`, device memory.
  *   rf_dot:      s[slot] = a.b
- *   rf_cg_q_dot: q = p + w;  s[RF_CG_PQ] = p.q
+ *   rf_cg_q_dot: q = p + w;  s[RF_CG_PQ] = p.q  (q may be NULL: not stored)
  *   rf_cg_step:  a = s[RF_CG_RR] / s[RF_CG_PQ] (0 if s[RF_CG_PQ] <= 0);
  *                v += a p;  r -= a q;  s[RF_CG_RR_NEW] = r.r
+ *   rf_cg_step_pw: the same with q = p + w formed on the fly (A p = p + w for
+ *                the system of Sec. 2.1, so q need not be stored)
  *   rf_cg_dir:   p = r + (s[RF_CG_RR_NEW] / s[RF_CG_RR]) p;  s[RF_CG_RR] = s[RF_CG_RR_NEW]
  *   rf_axpy:     y += a x  (the gradient v + V^T H^T rd, the Hessian product p + w)
  * Asynchronous on `stream`; no allocation.  RF_E_ARG on null pointers,
@@ -247,6 +249,8 @@ int rf_cg_q_dot(rf_prec prec, int64_t n, const void *p, const void *w, void *q, 
                 void *stream);
 int rf_cg_step(rf_prec prec, int64_t n, const void *p, const void *q, void *v, void *r, void *work, double *s,
                void *stream);
+int rf_cg_step_pw(rf_prec prec, int64_t n, const void *p, const void *w, void *v, void *r, void *work, double *s,
+                  void *stream);
 int rf_cg_dir(rf_prec prec, int64_t n, const void *r, void *p, double *s, void *stream);
 int rf_axpy(rf_prec prec, int64_t n, double a, const void *x, void *y, void *stream);
 

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kCgThreads) void k_dot(const T *__restrict__ a, con
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// q = p + w; partial sums of p.q
+// q = p + w (not stored when q is null); partial sums of p.q
 template <class T>
 __global__ __launch_bounds__(kCgThreads) void k_q_dot(const T *__restrict__ p, const T *__restrict__ w,
                                                      T *__restrict__ q, double *__restrict__ partial, long n)
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kCgThreads) void k_q_dot(const T *__restrict__ p, c
     double acc = 0.0;
     for (long i = (long)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += (long)kCgBlocks * kCgThreads) {
         const T pi = ld(p + i), qi = pi + ld(w + i);
-        st(q + i, qi);
+        if (q) st(q + i, qi);
         acc += (double)pi * (double)qi;
     }
     const double s = block_sum(acc, sh);
@@ -72,6 +72,28 @@ __global__ __launch_bounds__(kCgThreads) void k_step(const T *__restrict__ p, co
     for (long i = (long)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += (long)kCgBlocks * kCgThreads) {
         st(v + i, ld(v + i) + a * ld(p + i));
         const T ri = ld(r + i) - a * ld(q + i);
+        st(r + i, ri);
+        acc += (double)ri * (double)ri;
+    }
+    const double sum = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+
+// a = s[RR] / s[PQ]; v += a p; r -= a (p + w); partial sums of r.r
+template <class T>
+__global__ __launch_bounds__(kCgThreads) void k_step_pw(const T *__restrict__ p, const T *__restrict__ w,
+                                                       T *__restrict__ v, T *__restrict__ r,
+                                                       const double *__restrict__ s, double *__restrict__ partial,
+                                                       long n)
+{
+    __shared__ double sh[kCgThreads];
+    const double pq = s[RF_CG_PQ];
+    const T a = pq > 0.0 ? (T)(s[RF_CG_RR] / pq) : (T)0;
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += (long)kCgBlocks * kCgThreads) {
+        const T pi = ld(p + i);
+        st(v + i, ld(v + i) + a * pi);
+        const T ri = ld(r + i) - a * (pi + ld(w + i));
         st(r + i, ri);
         acc += (double)ri * (double)ri;
     }
@@ -137,7 +159,7 @@ extern "C" int rf_dot(rf_prec prec, int64_t n, const void *a, const void *b, voi
 extern "C" int rf_cg_q_dot(rf_prec prec, int64_t n, const void *p, const void *w, void *q, void *work, double *s,
                            void *stream)
 {
-    if (!args_ok(prec, n, p, w) || !q || !work || !s) return RF_E_ARG;
+    if (!args_ok(prec, n, p, w) || !work || !s) return RF_E_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     double *part = static_cast<double *>(work);
     if (prec == RF_FP32)
@@ -185,5 +207,21 @@ extern "C" int rf_axpy(rf_prec prec, int64_t n, double a, const void *x, void *y
         k_axpy<float><<<kCgBlocks, kCgThreads, 0, st>>>((float)a, (const float *)x, (float *)y, n);
     else
         k_axpy<double><<<kCgBlocks, kCgThreads, 0, st>>>(a, (const double *)x, (double *)y, n);
+    return hipGetLastError() == hipSuccess ? RF_OK : RF_E_HIP;
+}
+
+extern "C" int rf_cg_step_pw(rf_prec prec, int64_t n, const void *p, const void *w, void *v, void *r, void *work,
+                             double *s, void *stream)
+{
+    if (!args_ok(prec, n, p, w) || !v || !r || !work || !s) return RF_E_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    double *part = static_cast<double *>(work);
+    if (prec == RF_FP32)
+        k_step_pw<float><<<kCgBlocks, kCgThreads, 0, st>>>((const float *)p, (const float *)w, (float *)v,
+                                                           (float *)r, s, part, n);
+    else
+        k_step_pw<double><<<kCgBlocks, kCgThreads, 0, st>>>((const double *)p, (const double *)w, (double *)v,
+                                                            (double *)r, s, part, n);
+    k_finish<<<1, kCgThreads, 0, st>>>(part, s, RF_CG_RR_NEW);
     return hipGetLastError() == hipSuccess ? RF_OK : RF_E_HIP;
 }

@@ -105,6 +105,8 @@ def lib() -> ctypes.CDLL:
         L.rf_cg_q_dot.argtypes = [I, L64, P, P, P, P, P, P]
         L.rf_cg_step.restype = I
         L.rf_cg_step.argtypes = [I, L64, P, P, P, P, P, P, P]
+        L.rf_cg_step_pw.restype = I
+        L.rf_cg_step_pw.argtypes = [I, L64, P, P, P, P, P, P, P]
         L.rf_cg_dir.restype = I
         L.rf_cg_dir.argtypes = [I, L64, P, P, P, P]
         L.rf_axpy.restype = I
@@ -286,6 +288,11 @@ def rf_cg_q_dot(prec, n, p, w, q, work, s, stream=None):
 def rf_cg_step(prec, n, p, q, v, r, work, s, stream=None):
     _check(lib().rf_cg_step(int(prec), int(n), _ptr(p), _ptr(q), _ptr(v), _ptr(r), _ptr(work), _ptr(s),
                             _stream(stream)), "rf_cg_step")
+
+
+def rf_cg_step_pw(prec, n, p, w, v, r, work, s, stream=None):
+    _check(lib().rf_cg_step_pw(int(prec), int(n), _ptr(p), _ptr(w), _ptr(v), _ptr(r), _ptr(work), _ptr(s),
+                               _stream(stream)), "rf_cg_step_pw")
 
 
 def rf_cg_dir(prec, n, r, p, s, stream=None):

@@ -132,13 +132,12 @@ class Var3D:
         v = torch.zeros(self.obs.shape, dtype=self.y.dtype, device=self.y.device)
         r = self.op.adjoint(self.obs.adjoint(self._innov(None, self.y, -1.0)))   # V^T H^T R^-1 y
         p = r.clone()
-        q = torch.empty_like(p)
         rf3.rf_dot(self.prec, n, r, r, self.work, self.s, rf3.RF_CG_RR)
         costs = [self.cost_grad(v)[0]]
         for k in range(iters):
-            w = self._vthv(p)
-            rf3.rf_cg_q_dot(self.prec, n, p, w, q, self.work, self.s)       # q = p + w, p.q
-            rf3.rf_cg_step(self.prec, n, p, q, v, r, self.work, self.s)     # v += a p, r -= a q, r.r
+            w = self._vthv(p)                                                # A p = p + w
+            rf3.rf_cg_q_dot(self.prec, n, p, w, None, self.work, self.s)    # p.(p + w)
+            rf3.rf_cg_step_pw(self.prec, n, p, w, v, r, self.work, self.s)  # v += a p, r -= a (p + w), r.r
             rf3.rf_cg_dir(self.prec, n, r, p, self.s)                       # p = r + b p
             if track_cost:
                 costs.append(self.cost_grad(v)[0])

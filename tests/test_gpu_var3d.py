@@ -98,8 +98,11 @@ def test_autograd_backward_is_the_adjoint(grid, orc):
 def test_gradcheck_fp64():
     w = synth.random_case(32, 8, 10, 1, 0.2, 2, (1.5, 4.0), 3.0, "fit", False, False)
     op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, 1, n_img=w.n_img, qmode=w.qmode, device=DEV)
-    x = torch.randn(1, 8, 10, device=DEV, dtype=torch.float64, requires_grad=True)
-    assert torch.autograd.gradcheck(lambda t: rf3xy(t, op), (x,), eps=1e-6, atol=1e-9, rtol=1e-7)
+    gen = torch.Generator(device=DEV).manual_seed(5)
+    x = torch.randn(1, 8, 10, generator=gen, device=DEV, dtype=torch.float64).requires_grad_(True)
+    # outputs reach ~1e2 (gain 2 pi sigma_x sigma_y), so the central differences carry
+    # rounding of ~1e-8; a wrong adjoint is off by O(1)
+    assert torch.autograd.gradcheck(lambda t: rf3xy(t, op), (x,), eps=1e-6, atol=1e-8, rtol=1e-6)
 
 
 @pytest.fixture(scope="module")
@@ -183,6 +186,18 @@ def test_cg_vector_kernels(dtype):
     rf3.rf_cg_dir(prec, n, r, p, s)
     assert rel(p.double().cpu().numpy(), rn + b * P) < tol
     assert float(s[rf3.RF_CG_RR]) == float(s[rf3.RF_CG_RR_NEW])
+    # q not stored, and the step with q = p + w formed on the fly
+    p2, w2, v2, r2 = (torch.randn(n, generator=gen, device=DEV, dtype=dtype) for _ in range(4))
+    P2, W2, V2, R2 = (t.double().cpu().numpy() for t in (p2, w2, v2, r2))
+    rf3.rf_dot(prec, n, r2, r2, work, s, rf3.RF_CG_RR)
+    rf3.rf_cg_q_dot(prec, n, p2, w2, None, work, s)
+    assert abs(float(s[rf3.RF_CG_PQ]) - P2 @ (P2 + W2)) <= 1e-6 * abs(P2 @ (P2 + W2))
+    a2 = float(s[rf3.RF_CG_RR]) / float(s[rf3.RF_CG_PQ])
+    rf3.rf_cg_step_pw(prec, n, p2, w2, v2, r2, work, s)
+    assert rel(v2.double().cpu().numpy(), V2 + a2 * P2) < tol
+    assert rel(r2.double().cpu().numpy(), R2 - a2 * (P2 + W2)) < tol
+    rn2 = r2.double().cpu().numpy()
+    assert abs(float(s[rf3.RF_CG_RR_NEW]) - rn2 @ rn2) <= 1e-12 * (rn2 @ rn2)
     # y += a x
     x, y = (torch.randn(n, generator=gen, device=DEV, dtype=dtype) for _ in range(2))
     X, Y = (t.double().cpu().numpy() for t in (x, y))

@@ -123,8 +123,8 @@ def bench_cg(torch, dev, w, op, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
     ap.add_argument("--cpu-levels", type=int, default=0,
                     help="levels of the workload the CPU oracle runs on (0 = all levels)")

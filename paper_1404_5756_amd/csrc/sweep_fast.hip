@@ -465,13 +465,14 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x_batch(
 // ======================================================================
 // y direction: 16 waves per block of 64 columns; wave w owns rows
 // [w*L, w*L + L), lane = column, and every lane carries P planes (P = 2 when
-// L <= 45) so that each coefficient load serves P recurrences.  The chunk
-// transfer matrices (per column, chunk and sweep) come from the coefficient
-// block; local end states pass between the waves through LDS.  Coefficients
-// are read one row at a time through a rolling window.  A workgroup loops
-// over the plane groups of its column block.  Row offsets are scalar buffer
-// offsets, clamped to the grid: rows past the end are outside every segment
-// (their input is masked off and they are never stored).
+// L <= 45) so that each coefficient load serves P recurrences.  The local
+// passes are dot products with precomputed K vectors; the chunk transfer
+// matrices (per column, chunk and sweep) come from the coefficient block, and
+// local end states pass between the waves through LDS.  Coefficients and K
+// vectors are read one row at a time through a rolling window.  A workgroup
+// takes a contiguous range of planes of its column block.  Row offsets are
+// scalar buffer offsets, clamped to the grid: rows past the end are outside
+// every segment (their input is masked off and they are never stored).
 // ======================================================================
 constexpr int kYWin = 2;
 

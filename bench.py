@@ -30,6 +30,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c3.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1404_5756_amd", "csrc", "sweep_fast.hip")
 
 
+def kernel_code_hash(path=KERNEL_SRC):
+    """sha256 of the kernel source without comments and blank space: the traffic
+    figures stay valid across comment-only edits, not across code changes."""
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    src = "\n".join(" ".join(line.split()) for line in src.splitlines() if line.strip())
+    return hashlib.sha256(src.encode()).hexdigest()
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -202,8 +213,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         # '#' lines are commentary; the rest is one JSON object written from rocprofv3 counters
         tf = json.loads("".join(l for l in open(TRAFFIC_FILE) if not l.lstrip().startswith("#")))
-        src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if tf.get("kernel_src_sha256") == src_hash and dom in tf.get("bytes_per_launch", {}):
+        src_hash = kernel_code_hash()
+        if tf.get("kernel_code_sha256") == src_hash and dom in tf.get("bytes_per_launch", {}):
             traffic = tf["bytes_per_launch"][dom]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,

@@ -682,12 +682,13 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
 }
 
 // Planes [pa, pb) of one column block: units of two planes (one when L > 45),
-// and a one-plane unit for an odd count, run first when single_first is set
-// (so that neighbouring workgroups do not reach their memory phases together).
+// and a one-plane unit for an odd count, run after single_after two-plane
+// units (varied across workgroups, so that they do not all reach their memory
+// phases together).
 template <int L, bool ADJ>
 __device__ __forceinline__ void y_planes(const float *in, float *out, const float4 *T, const float *KY,
                                          const uint64_t *LM, const float *PHI, int nx, int ny, int blk, int pa, int pb,
-                                         bool single_first, float (*phi)[kYWaves][kYCols * 9], float *bsh)
+                                         int single_after, float (*phi)[kYWaves][kYCols * 9], float *bsh)
 {
     constexpr int PM = y_planes_per_lane(L);
     {
@@ -700,19 +701,22 @@ __device__ __forceinline__ void y_planes(const float *in, float *out, const floa
         }
     }
     __syncthreads();
-    if (PM == 2 && single_first && ((pb - pa) & 1)) {
-        y_unit<L, ADJ, 1>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
-        ++pa;
+    for (int k = 0; pa < pb; ++k) {
+        // an odd count leaves one one-plane unit: it runs after single_after pairs
+        const bool single = PM == 1 || pb - pa == 1 || (((pb - pa) & 1) && k >= single_after);
+        if (single) {
+            y_unit<L, ADJ, 1>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
+            pa += 1;
+        } else {
+            y_unit<L, ADJ, PM>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
+            pa += PM;
+        }
         __syncthreads();   // bsh is rewritten by the next unit
     }
-    for (; pa + PM <= pb; pa += PM) {
-        y_unit<L, ADJ, PM>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
-        __syncthreads();
-    }
-    if (pa < pb) y_unit<L, ADJ, 1>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
 }
 
-// Workgroup (column block, slot): slot j of S takes planes [j n / S, (j+1) n / S).
+// Workgroup (column block, slot): slot j of S takes planes [j n / S, (j+1) n / S),
+// its one-plane unit (odd counts) after (j + 2) % 3 two-plane units.
 template <int L, bool ADJ>
 __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float *out, const float4 *T,
                                                          const float *KY, const uint64_t *__restrict__ LM,
@@ -726,7 +730,7 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float
     const int blk = (slot / nslot) * 8 + xcd, j = slot % nslot;
     if (blk >= nblk) return;
     const int pa = (int)((long)j * nplanes / nslot), pb = (int)((long)(j + 1) * nplanes / nslot);
-    y_planes<L, ADJ>(in, out, T, KY, LM, PHI, nx, ny, blk, pa, pb, (j & 1) != 0, phi, bsh);
+    y_planes<L, ADJ>(in, out, T, KY, LM, PHI, nx, ny, blk, pa, pb, (j + 2) % 3, phi, bsh);
 }
 
 // Batched form: one workgroup per work unit {item, column block, first and end plane}.
@@ -741,7 +745,8 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_batch(const BatchEntry
     if (item < 0) return;
     const BatchEntry *e = E + item;
     y_planes<L, ADJ>(uni(src_out ? (const float *)e->out : e->in), uni(e->out), uni(e->T[1]), uni(e->KY), uni(e->LM[1]),
-                     uni(e->PHI[1]), uni(e->nx), uni(e->ny), uni(up->a), uni(up->b), uni(up->c), false, phi, bsh);
+                     uni(e->PHI[1]), uni(e->nx), uni(e->ny), uni(up->a), uni(up->b), uni(up->c), 1 << 30, phi,
+                     bsh);
 }
 
 // ---------------------------------------------------------------- setup

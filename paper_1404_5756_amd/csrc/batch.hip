@@ -1,7 +1,7 @@
 // Batched application of V_H (or its adjoint) to many grids in one go: the
 // fields, levels and uneven grids of all items become one work list of x rows
-// and y column blocks, run by one persistent work-list launch per (direction,
-// tile size).  The work list ("plan") is built on the host from the items and
+// and y column blocks, run by one work-list launch per occupancy class of the
+// x tile sizes and one for all y units.  The work list ("plan") is built on the host from the items and
 // the block layout alone; the caller copies it to device memory once.  Items
 // whose mask or sigma vary with level run the line-sequential path.
 #include <algorithm>
@@ -133,12 +133,20 @@ int build(const rf_batch_item *items, int32_t n, const rf_batch_tuning *tuning, 
             yl.push_back(std::move(c));
         }
     }
-    for (int dir = 0; dir < 2; ++dir)
-        for (const auto &kv : (dir == 0 ? xc : yc)) {
-            const int off = (int)P.units.size();
-            emit_xcd(kv.second, P.units);
-            P.groups.push_back(Group{dir, kv.first, off, (int)P.units.size() - off});
-        }
+    // x groups per tile size, largest first; the groups of one occupancy class
+    // run in one launch
+    for (auto it = xc.rbegin(); it != xc.rend(); ++it) {
+        const int off = (int)P.units.size();
+        emit_xcd(it->second, P.units);
+        P.groups.push_back(Group{0, it->first, off, (int)P.units.size() - off});
+    }
+    // y groups from the largest tile size down: their units run in one launch,
+    // and the short units of small tiles fill its last round
+    for (auto it = yc.rbegin(); it != yc.rend(); ++it) {
+        const int off = (int)P.units.size();
+        emit_xcd(it->second, P.units);
+        P.groups.push_back(Group{1, it->first, off, (int)P.units.size() - off});
+    }
     if (P.units.size() > (size_t)INT32_MAX / 2) return RF_E_SHAPE;
     P.off_entries = sizeof(PlanHeader);
     P.off_units = (P.off_entries + P.entries.size() * sizeof(BatchEntry) + 255) & ~size_t(255);
@@ -215,15 +223,29 @@ extern "C" int rf3_apply_batch_ex(const rf_batch_item *items, int32_t n, const r
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const BatchEntry *E = at<const BatchEntry>(plan_dev, P.off_entries);
     const BatchUnit *U = at<const BatchUnit>(plan_dev, P.off_units);
-    // forward: all x groups, then all y groups reading the x output; adjoint: y first
+    // the y groups follow the x groups in the work list, one after another
+    int y_off = (int)P.units.size();
+    for (const Group &gr : P.groups)
+        if (gr.dir == 1) y_off = std::min(y_off, gr.offset);
+    // forward: all x groups, then all y units reading the x output; adjoint: y first
     for (int pass = 0; pass < 2; ++pass) {
         const int dir = adj ? 1 - pass : pass;
-        for (const Group &gr : P.groups) {
-            if (gr.dir != dir) continue;
-            const hipError_t e = dir == 0 ? fast_rf3_x_batch(E, U + gr.offset, gr.count, gr.L, adj, pass == 1, st)
-                                          : fast_rf3_y_batch(E, U + gr.offset, gr.count, gr.L, adj, pass == 1, st);
-            if (e != hipSuccess) return RF_E_HIP;
+        hipError_t e = hipSuccess;
+        if (dir == 1) {
+            e = fast_rf3_y_batch(E, U + y_off, (int)P.units.size() - y_off, adj, pass == 1, st);
+        } else {
+            // consecutive x groups of one occupancy class make one launch
+            for (size_t k = 0; k < P.groups.size() && e == hipSuccess;) {
+                const Group &gr = P.groups[k];
+                if (gr.dir != 0) { ++k; continue; }
+                const int cls = x_batch_class(gr.L);
+                int count = 0;
+                for (; k < P.groups.size() && P.groups[k].dir == 0 && x_batch_class(P.groups[k].L) == cls; ++k)
+                    count += P.groups[k].count;
+                e = fast_rf3_x_batch(E, U + gr.offset, count, cls, adj, pass == 1, st);
+            }
         }
+        if (e != hipSuccess) return RF_E_HIP;
     }
     for (int i : P.seq_items) {
         const int r = rf3_run(items[i].g, items[i].coef, prec, items[i].in, items[i].out, items[i].g->nlev,

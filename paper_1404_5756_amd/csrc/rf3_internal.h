@@ -68,6 +68,9 @@ __host__ __device__ inline int tile_lx(int nx)
     if (need > kLxMax) return 0;
     return need | 1;
 }
+// batched x launches group the tile sizes by occupancy: the class is its
+// largest tile size (the x kernels' registers and LDS grow with the tile)
+__host__ __device__ constexpr int x_batch_class(int lx) { return lx <= 3 ? 3 : lx <= 11 ? 11 : lx <= 23 ? 23 : 33; }
 // padded per-row length of the x lane-mask arrays (whole 8-entry blocks)
 __host__ __device__ inline int lmx_stride(int lx) { return (lx + 7) & ~7; }
 // per-column-block length of the y lane-mask arrays: 8 guard entries before row

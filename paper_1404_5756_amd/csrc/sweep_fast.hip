@@ -447,20 +447,41 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
 
 // Batched form: one workgroup per work unit {item, row, group, groups}; the
 // second pass of a V_H application reads the first pass's output (src_out).
-template <int L, bool ADJ>
-__global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x_batch(
+// One launch serves every tile size of an occupancy class (x_batch_class):
+// the class's largest tile sets the LDS staging area and the register budget,
+// which the smaller tiles of the class fit without losing occupancy.
+#define RF_XB_UNIT(Lv)                                                                                    \
+    case Lv:                                                                                              \
+        if constexpr (x_batch_class(Lv) == LMAX)                                                          \
+            x_rows<Lv, ADJ>(in, out, T, LM, PHI, nx, ny, nplanes, row, grp, groups, K, stg);              \
+        break;
+
+template <int LMAX, bool ADJ>
+__global__ __launch_bounds__(64 * kXWaves, (LMAX <= 23 ? 3 : 2)) void k_rf3x_batch(
     const BatchEntry *__restrict__ E, const BatchUnit *__restrict__ U, int src_out)
 {
     __shared__ float K[2 * 64 * kKs];
-    __shared__ __align__(16) float stage[kXWaves][x_stage_floats<L>()];
+    __shared__ __align__(16) float stage[kXWaves][x_stage_floats<LMAX>()];
     const BatchUnit *up = U + blockIdx.x;
     const int item = uni(up->item);
     if (item < 0) return;
     const BatchEntry *e = E + item;
-    x_rows<L, ADJ>(uni(src_out ? (const float *)e->out : e->in), uni(e->out), uni(e->T[0]), uni(e->LM[0]),
-                   uni(e->PHI[0]), uni(e->nx), uni(e->ny), uni(e->nplanes), uni(up->a), uni(up->b), uni(up->c), K,
-                   stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+    const float *in = uni(src_out ? (const float *)e->out : e->in);
+    float *out = uni(e->out);
+    const float4 *T = uni(e->T[0]);
+    const uint64_t *LM = uni(e->LM[0]);
+    const float *PHI = uni(e->PHI[0]);
+    const int nx = uni(e->nx), ny = uni(e->ny), nplanes = uni(e->nplanes);
+    const int row = uni(up->a), grp = uni(up->b), groups = uni(up->c);
+    float *stg = stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
+    switch (tile_lx(nx)) {
+        RF_XB_UNIT(1) RF_XB_UNIT(3) RF_XB_UNIT(5) RF_XB_UNIT(7) RF_XB_UNIT(9) RF_XB_UNIT(11) RF_XB_UNIT(13)
+        RF_XB_UNIT(15) RF_XB_UNIT(17) RF_XB_UNIT(19) RF_XB_UNIT(21) RF_XB_UNIT(23) RF_XB_UNIT(25) RF_XB_UNIT(27)
+        RF_XB_UNIT(29) RF_XB_UNIT(31) RF_XB_UNIT(33)
+    default: break;
+    }
 }
+#undef RF_XB_UNIT
 
 // ======================================================================
 // y direction: 16 waves per block of 64 columns; wave w owns rows
@@ -733,8 +754,16 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float
     y_planes<L, ADJ>(in, out, T, KY, LM, PHI, nx, ny, blk, pa, pb, (j + 2) % 3, phi, bsh);
 }
 
-// Batched form: one workgroup per work unit {item, column block, first and end plane}.
-template <int L, bool ADJ>
+// Batched form: one workgroup per work unit {item, column block, first and end
+// plane}.  The tile size follows from the item's ny, so one launch serves the
+// units of every tile size (the work list puts the largest tiles first and the
+// small units fill the last round).
+#define RF_YB_UNIT(Lv)                                                                                    \
+    case Lv:                                                                                              \
+        y_planes<Lv, ADJ>(in, out, T, KY, LM, PHI, nx, ny, blk, pa, pb, 1 << 30, phi, bsh);               \
+        break;
+
+template <bool ADJ>
 __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_batch(const BatchEntry *__restrict__ E,
                                                                const BatchUnit *__restrict__ U, int src_out)
 {
@@ -744,10 +773,21 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_batch(const BatchEntry
     const int item = uni(up->item);
     if (item < 0) return;
     const BatchEntry *e = E + item;
-    y_planes<L, ADJ>(uni(src_out ? (const float *)e->out : e->in), uni(e->out), uni(e->T[1]), uni(e->KY), uni(e->LM[1]),
-                     uni(e->PHI[1]), uni(e->nx), uni(e->ny), uni(up->a), uni(up->b), uni(up->c), 1 << 30, phi,
-                     bsh);
+    const float *in = uni(src_out ? (const float *)e->out : e->in);
+    float *out = uni(e->out);
+    const float4 *T = uni(e->T[1]);
+    const float *KY = uni(e->KY);
+    const uint64_t *LM = uni(e->LM[1]);
+    const float *PHI = uni(e->PHI[1]);
+    const int nx = uni(e->nx), ny = uni(e->ny), blk = uni(up->a), pa = uni(up->b), pb = uni(up->c);
+    switch (tile_ly(ny)) {
+        RF_YB_UNIT(1) RF_YB_UNIT(2) RF_YB_UNIT(3) RF_YB_UNIT(4) RF_YB_UNIT(6) RF_YB_UNIT(8) RF_YB_UNIT(12)
+        RF_YB_UNIT(16) RF_YB_UNIT(20) RF_YB_UNIT(24) RF_YB_UNIT(28) RF_YB_UNIT(32) RF_YB_UNIT(36) RF_YB_UNIT(40)
+        RF_YB_UNIT(45) RF_YB_UNIT(48) RF_YB_UNIT(56) RF_YB_UNIT(64)
+    default: break;
+    }
 }
+#undef RF_YB_UNIT
 
 // ---------------------------------------------------------------- setup
 // 3x3 transfer matrix of one chunk of n points, FP64 from the FP32 table.
@@ -1003,39 +1043,39 @@ hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float 
     }
 }
 
-#define RF_XB_CASE(Lv)                                                                                    \
-    case Lv:                                                                                              \
-        if (adj) k_rf3x_batch<Lv, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);                  \
-        else k_rf3x_batch<Lv, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);                     \
-        return hipGetLastError();
-#define RF_YB_CASE(Lv)                                                                                    \
-    case Lv:                                                                                              \
-        if (adj) k_rf3y_batch<Lv, true><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out);                  \
-        else k_rf3y_batch<Lv, false><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out);                     \
-        return hipGetLastError();
-
-hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int lx, bool adj, bool src_out,
+hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int cls, bool adj, bool src_out,
                             hipStream_t st)
 {
     if (nunits <= 0) return hipSuccess;
-    switch (lx) {
-        RF_XB_CASE(1) RF_XB_CASE(3) RF_XB_CASE(5) RF_XB_CASE(7) RF_XB_CASE(9) RF_XB_CASE(11) RF_XB_CASE(13)
-        RF_XB_CASE(15) RF_XB_CASE(17) RF_XB_CASE(19) RF_XB_CASE(21) RF_XB_CASE(23) RF_XB_CASE(25) RF_XB_CASE(27)
-        RF_XB_CASE(29) RF_XB_CASE(31) RF_XB_CASE(33)
+    switch (cls) {
+    case 3:
+        if (adj) k_rf3x_batch<3, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        else k_rf3x_batch<3, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        break;
+    case 11:
+        if (adj) k_rf3x_batch<11, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        else k_rf3x_batch<11, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        break;
+    case 23:
+        if (adj) k_rf3x_batch<23, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        else k_rf3x_batch<23, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        break;
+    case 33:
+        if (adj) k_rf3x_batch<33, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        else k_rf3x_batch<33, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        break;
     default: return hipErrorNotSupported;
     }
+    return hipGetLastError();
 }
 
-hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int ly, bool adj, bool src_out,
+hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits, bool adj, bool src_out,
                             hipStream_t st)
 {
     if (nunits <= 0) return hipSuccess;
-    switch (ly) {
-        RF_YB_CASE(1) RF_YB_CASE(2) RF_YB_CASE(3) RF_YB_CASE(4) RF_YB_CASE(6) RF_YB_CASE(8) RF_YB_CASE(12)
-        RF_YB_CASE(16) RF_YB_CASE(20) RF_YB_CASE(24) RF_YB_CASE(28) RF_YB_CASE(32) RF_YB_CASE(36) RF_YB_CASE(40)
-        RF_YB_CASE(45) RF_YB_CASE(48) RF_YB_CASE(56) RF_YB_CASE(64)
-    default: return hipErrorNotSupported;
-    }
+    if (adj) k_rf3y_batch<true><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out);
+    else k_rf3y_batch<false><<<nunits, 64 * kYWaves, 0, st>>>(E, U, src_out);
+    return hipGetLastError();
 }
 
 hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int lx, hipStream_t st)

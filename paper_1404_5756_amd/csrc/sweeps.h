@@ -31,10 +31,12 @@ hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64
                       int nx, int ny, int nplanes, bool adj, hipStream_t st);
 hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
                       const float *PHI, int ly, int nx, int ny, int nplanes, bool adj, hipStream_t st);
-// batched forms over a work list (all units of one launch share the tile size)
-hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int lx, bool adj, bool src_out,
+// batched forms over a work list: x units of one launch share the occupancy
+// class of their tile size (x_batch_class), a y launch takes units of any tile
+// size; each unit's tile size follows from its item's nx or ny
+hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int cls, bool adj, bool src_out,
                             hipStream_t st);
-hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int ly, bool adj, bool src_out,
+hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits, bool adj, bool src_out,
                             hipStream_t st);
 int x_groups(int ny, int nplanes, int gmax);
 hipError_t setup_phi_y(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int ly, hipStream_t st);

@@ -95,6 +95,11 @@ def test_units_cover_every_row_and_plane_once():
         # y units: {item, column block, first plane, end plane}
         cover = sorted((u[1], q) for u in yu if u[0] == k for q in range(u[2], u[3]))
         assert cover == [(b, q) for b in range(-(-g.nx // 64)) for q in range(g.nlev * nf)]
+    # largest tiles first in each direction: a launch's short units come last and fill its final round
+    lxs = [_tile_lx(items[u[0]][0].nx) for u in xu]
+    lys = [_tile_ly(items[u[0]][0].ny) for u in yu]
+    assert lxs == sorted(lxs, reverse=True) and len(set(lxs)) == 3
+    assert lys == sorted(lys, reverse=True) and len(set(lys)) == 3
 
 
 def test_plan_errors():

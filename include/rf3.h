@@ -134,8 +134,8 @@ int rf1_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, int32_t K,
  * all g->nlev levels of its grid.
  *
  * The x rows and y column blocks of all items form one work list; it runs as
- * one persistent work-list launch per (direction, tile size) -- a handful of
- * launches for any number of items.  Items whose mask or sigma vary with
+ * one y launch and at most four x launches (one per occupancy class of the x
+ * tile sizes) per direction, for any number of items.  Items whose mask or sigma vary with
  * level (mask_nlev or sigma_nlev > 1) run the line-sequential path instead.
  *
  * Two steps, so that the apply step can be captured into a hipGraph:

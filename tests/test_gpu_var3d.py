@@ -152,13 +152,20 @@ def test_cg_monotone_and_matches_reference(problems, orc, grid):
     assert rel(v32.double().cpu().numpy().ravel(), its[-1]) < 1e-4
 
 
+@pytest.mark.parametrize("offset", [0, 1])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-def test_cg_vector_kernels(dtype):
+def test_cg_vector_kernels(dtype, offset):
+    """The vector kernels stream 16-byte elements plus a scalar tail (n is odd); with offset 1
+    every vector starts one entry past a 16-byte boundary and the scalar loop takes it all."""
     from paper_1404_5756_amd import rf3
     prec = rf3.RF_FP32 if dtype == torch.float32 else rf3.RF_FP64
     gen = torch.Generator(device=DEV).manual_seed(9)
     n = 1_000_003
-    p, w, v, r = (torch.randn(n, generator=gen, device=DEV, dtype=dtype) for _ in range(4))
+
+    def vec():
+        return torch.randn(n + offset, generator=gen, device=DEV, dtype=dtype)[offset:]
+
+    p, w, v, r = (vec() for _ in range(4))
     s = torch.zeros(rf3.RF_CG_SLOTS, dtype=torch.float64, device=DEV)
     work = torch.empty(rf3.rf_cg_work_bytes() // 8, dtype=torch.float64, device=DEV)
     P, W, Vv, Rr = (t.double().cpu().numpy() for t in (p, w, v, r))
@@ -187,7 +194,7 @@ def test_cg_vector_kernels(dtype):
     assert rel(p.double().cpu().numpy(), rn + b * P) < tol
     assert float(s[rf3.RF_CG_RR]) == float(s[rf3.RF_CG_RR_NEW])
     # q not stored, and the step with q = p + w formed on the fly
-    p2, w2, v2, r2 = (torch.randn(n, generator=gen, device=DEV, dtype=dtype) for _ in range(4))
+    p2, w2, v2, r2 = (vec() for _ in range(4))
     P2, W2, V2, R2 = (t.double().cpu().numpy() for t in (p2, w2, v2, r2))
     rf3.rf_dot(prec, n, r2, r2, work, s, rf3.RF_CG_RR)
     rf3.rf_cg_q_dot(prec, n, p2, w2, None, work, s)
@@ -199,7 +206,7 @@ def test_cg_vector_kernels(dtype):
     rn2 = r2.double().cpu().numpy()
     assert abs(float(s[rf3.RF_CG_RR_NEW]) - rn2 @ rn2) <= 1e-12 * (rn2 @ rn2)
     # y += a x
-    x, y = (torch.randn(n, generator=gen, device=DEV, dtype=dtype) for _ in range(2))
+    x, y = (vec() for _ in range(2))
     X, Y = (t.double().cpu().numpy() for t in (x, y))
     rf3.rf_axpy(prec, n, -0.75, x, y)
     assert rel(y.double().cpu().numpy(), Y - 0.75 * X) < tol

@@ -138,11 +138,18 @@ __global__ void k_obs_innov(const ObsPlanHeader *__restrict__ hd, const int32_t 
     rd[o] = (rinv ? rinv[o] : (T)1) * scale * s;
 }
 
+// f[0, n) = 0: 16-byte stores over the first nv 16-byte elements (nv is 0 when
+// f is not 16-byte aligned), then single entries.  Streamed once, so the stores
+// are non-temporal and leave L2 to the covariance operator's tables.
 template <class T>
-__global__ void k_fill(T *__restrict__ f, long n)
+__global__ void k_fill(T *__restrict__ f, long n, long nv)
 {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        __builtin_nontemporal_store((T)0, f + i);   // streamed once: keep L2 for the tables
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const long t0 = (long)blockIdx.x * blockDim.x + threadIdx.x, stride = (long)gridDim.x * blockDim.x;
+    u32x4 *fv = reinterpret_cast<u32x4 *>(f);
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (long i = t0; i < nv; i += stride) __builtin_nontemporal_store(z, fv + i);
+    for (long i = nv * (long)(16 / sizeof(T)) + t0; i < n; i += stride) __builtin_nontemporal_store((T)0, f + i);
 }
 
 template <class T>
@@ -242,12 +249,14 @@ extern "C" int rf_obs_adjoint(const void *plan_dev, int32_t nobs, int32_t nuniq,
     const unsigned nf = (unsigned)std::min<long>((npts + 255) / 256, 8192);
     const unsigned nb = (unsigned)((nuniq + 255) / 256);
     const ObsPlanHeader *hd = static_cast<const ObsPlanHeader *>(plan_dev);
+    const long es = prec == RF_FP32 ? 4 : 8;
+    const long nv = reinterpret_cast<uintptr_t>(field) % 16 ? 0 : npts * es / 16;
     if (prec == RF_FP32) {
-        k_fill<float><<<nf, 256, 0, st>>>((float *)field, npts);
+        k_fill<float><<<nf, 256, 0, st>>>((float *)field, npts, nv);
         k_obs_adjoint<float><<<nb, 256, 0, st>>>(hd, upt, uptr, ent, w, (const float *)obs, (float *)field, nobs,
                                                  nuniq, npts);
     } else {
-        k_fill<double><<<nf, 256, 0, st>>>((double *)field, npts);
+        k_fill<double><<<nf, 256, 0, st>>>((double *)field, npts, nv);
         k_obs_adjoint<double><<<nb, 256, 0, st>>>(hd, upt, uptr, ent, w, (const double *)obs, (double *)field, nobs,
                                                   nuniq, npts);
     }

@@ -76,6 +76,26 @@ def test_obs_innovation_matches_reference(grid, dtype):
     assert rel(rd.double().cpu().numpy(), hf - y) < tol
 
 
+@pytest.mark.parametrize("offset", [0, 1])
+def test_obs_adjoint_writes_every_point(offset):
+    """H^T clears its whole output first (16-byte stores plus single entries): an odd point
+    count, the output aligned or one entry past a 16-byte boundary, pre-filled with NaN."""
+    w = synth.random_case(33, 13, 17, 3, 0.3, 2, (1.5, 4.0), 3.0, "fit", False, False)
+    op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode, device=DEV)
+    lev, xs, ys = synth.c5_observations(w, 200, seed=12)
+    obs = Observations(op, lev, xs, ys)
+    idx, wt = ov.obs_weights(w.nx, w.ny, lev, xs, ys)
+    d = np.random.default_rng(5).standard_normal(len(lev))
+    npts = w.nlev * w.ny * w.nx
+    assert npts % 2 == 1
+    buf = torch.full((npts + offset,), float("nan"), device=DEV)
+    out = buf[offset:].view(w.nlev, w.ny, w.nx)
+    obs.adjoint(torch.from_numpy(d).to(DEV, torch.float32), out=out)
+    got = out.double().cpu().numpy().ravel()
+    assert np.isfinite(got).all()
+    assert rel(got, ov.obs_adjoint(d, idx, wt, npts)) < 1e-6
+
+
 def test_obs_adjoint_is_deterministic(grid):
     w, op, lev, xs, ys = grid
     obs = Observations(op, lev, xs, ys)

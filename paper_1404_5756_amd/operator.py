@@ -108,7 +108,7 @@ class Batch:
     """
 
     # candidate work-list shapes tried by autotune(): (x_groups_max, y_planes)
-    CANDIDATES = tuple((xg, yp) for xg in (1, 2, 4, 8, 16) for yp in (1, 2, 4, 8, 16))
+    CANDIDATES = tuple((xg, yp) for xg in (1, 2, 4, 8, 16) for yp in (1, 2, 3, 4, 6, 8, 16))
 
     def __init__(self, items, device=None, tuning=None):
         self._items = []

@@ -22,6 +22,7 @@ ITEMS = [
     (23, 40, 1100, 1, 2, False, False),
     (24, 60, 90, 3, 1, True, False),
     (25, 200, 333, 7, 1, False, False),
+    (26, 24, 1900, 2, 1, False, False),   # x tile 31: the batch's fourth x occupancy class
 ]
 
 

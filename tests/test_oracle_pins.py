@@ -254,11 +254,56 @@ def test_fig1_setting_rf1_converges_and_rf3_fit_beats_k5(orc):
     assert e_fit < errs[3]          # better than K = 5
 
 
-@pytest.mark.parametrize("sigma", [2.0, 4.0, 8.0, 12.0])
+@pytest.mark.parametrize("sigma", [1.5, 2.0, 4.0, 8.0, 12.0])
 def test_rf3_fit_beats_rf1_k5_over_the_sigma_range(orc, sigma):
     m = int(60 * sigma) | 1
     g = gaussian(m, sigma)
     assert shape_error(impulse(orc, m, sigma, 2), g) < shape_error(impulse(orc, m, sigma, op="rf1", K=5), g)
+
+
+def brute_rf1_iteration(al, be):
+    """One 1st-RF iteration on a segment from zero state at both ends (eqs. 'proc1-1', 'proc1-2'),
+    as dense solves: U^-1 D_beta L^-1 D_beta with (L)_{i,i-1} = -alpha_i, (U)_{i,i+1} = -alpha_i."""
+    m = be.size
+    L = np.eye(m) - np.diag(al[1:], -1)
+    U = np.eye(m) - np.diag(al[:-1], 1)
+    return np.linalg.solve(U, np.diag(be) @ np.linalg.solve(L, np.diag(be)))
+
+
+@pytest.mark.parametrize("n_img", [0, 1, 3])
+@pytest.mark.parametrize("K", [1, 3, 5])
+def test_rf1_masked_line_with_imaginary_points_is_brute_force(orc, n_img, K):
+    """1st-RF on a line with coasts: imaginary points take zero input in the first iteration, keep
+    their values between iterations and are zeroed in the output, so the line operator is
+    P_sea (block-diagonal over the extended segments of one-iteration operators)^K P_sea."""
+    rng = np.random.default_rng(40 + 7 * n_img + K)
+    for trial in range(6):
+        m = int(rng.integers(12, 48))
+        mask = (rng.uniform(size=m) > rng.uniform(0.15, 0.5)).astype(np.uint8)
+        mask[int(rng.integers(0, m))] = 1
+        sig = rng.uniform(1.2, 6.0, m)
+        P = line_problem(orc, sig, mask=mask, n_img=n_img)
+        G = dense_operator(orc, P, "rf1", K=K)
+        al, be = orc.coef1(sig, K)
+        B = np.zeros((m, m))
+        for a, e in brute_segments(list(mask), n_img):
+            B[a:e + 1, a:e + 1] = np.linalg.matrix_power(brute_rf1_iteration(al[a:e + 1], be[a:e + 1]), K)
+        sea = np.diag(mask.astype(float))
+        np.testing.assert_allclose(G, sea @ B @ sea, rtol=1e-12, atol=1e-14)
+        # the imaginary points matter once K > 1 or a trailing extension exists
+        if n_img > 0 and K > 1 and trial == 0:
+            B0 = np.zeros((m, m))
+            for a, e in brute_segments(list(mask), 0):
+                B0[a:e + 1, a:e + 1] = np.linalg.matrix_power(brute_rf1_iteration(al[a:e + 1], be[a:e + 1]), K)
+            assert np.abs(sea @ B0 @ sea - G).max() > 1e-6
+            # zeroing the imaginary points between iterations is a different operator
+            Bz = np.zeros((m, m))
+            for a, e in brute_segments(list(mask), n_img):
+                one = brute_rf1_iteration(al[a:e + 1], be[a:e + 1])
+                keep = np.diag(mask[a:e + 1].astype(float))
+                Bz[a:e + 1, a:e + 1] = np.linalg.matrix_power(keep @ one, K)
+            if np.any(mask == 0):
+                assert np.abs(sea @ Bz @ sea - G).max() > 1e-6
 
 
 # ---------------------------------------------------------------- coasts
@@ -348,6 +393,34 @@ def test_2d_adjoint_identity(orc, qmode):
     lhs = np.vdot(P.rf3(x), y)
     rhs = np.vdot(x, P.rf3_adjoint(y))
     assert lhs == pytest.approx(rhs, rel=1e-13)
+
+
+@pytest.mark.parametrize("op", ["rf3", "rf3_adjoint", "rf1"])
+def test_per_level_mask_and_sigma_slices_are_single_level_problems(orc, op):
+    """Depth-dependent mask and sigma (mask_nlev = sigma_nlev = nlev) with several fields: every
+    (field, level) slice of the output equals the single-level problem built from that level's
+    mask and sigma alone, and the 2-D broadcast form (mask_nlev = sigma_nlev = 1) equals per-level
+    tables that repeat the 2-D ones."""
+    rng = np.random.default_rng(31)
+    nf, nlev, ny, nx = 2, 3, 19, 26
+    mask = (rng.uniform(size=(nlev, ny, nx)) > np.array([0.2, 0.35, 0.5])[:, None, None]).astype(np.uint8)
+    sx = rng.uniform(1.2, 7.0, (nlev, ny, nx))
+    sy = rng.uniform(1.2, 7.0, (nlev, ny, nx))
+    x = rng.standard_normal((nf, nlev, ny, nx))
+    P = orc.Problem(mask, sx, sy, n_img=2, qmode=2, k1=3)
+    run = {"rf3": lambda Q, f: Q.rf3(f), "rf3_adjoint": lambda Q, f: Q.rf3_adjoint(f),
+           "rf1": lambda Q, f: Q.rf1(f, K=3)}[op]
+    out = run(P, x)
+    for k in range(nlev):
+        Q = orc.Problem(mask[k], sx[k], sy[k], n_img=2, qmode=2, k1=3)
+        for f in range(nf):
+            np.testing.assert_array_equal(out[f, k], run(Q, x[f, k]))
+    # levels really differ (a per-level table indexing slip would show here)
+    assert not np.array_equal(mask[0], mask[2])
+    P2 = orc.Problem(mask[1], sx[1], sy[1], n_img=2, qmode=2, k1=3)
+    Prep = orc.Problem(np.repeat(mask[1:2], nlev, 0), np.repeat(sx[1:2], nlev, 0), np.repeat(sy[1:2], nlev, 0),
+                       n_img=2, qmode=2, k1=3)
+    np.testing.assert_array_equal(run(P2, x), run(Prep, x))
 
 
 def test_2d_is_rows_then_columns(orc):

@@ -1,11 +1,12 @@
 """Parity at the full workload sizes, in the launch configuration bench.py times.
 
 C3 (1440 x 720 x 50, forward and adjoint), C2 (871 x 253 x 72, T and S,
-forward) and the C4 batch (64 grids, autotuned work list, hipGraph replay)
+forward and adjoint) and the C4 batch (64 grids, autotuned work list, hipGraph replay)
 against the FP64 C oracle.  C3 and C2 are compared at every output point (the
-oracle runs them in seconds with OpenMP); the C4 batch is compared with the
-per-item calls bitwise for all 64 grids and with the oracle on a spread of
-eight of them.  Tolerance: relative L2 1e-5 (FP32 path).
+oracle runs them in seconds with OpenMP), as one field-wide relative L2 and
+line by line (every x-row and y-column of every plane, parity_util); the C4
+batch is compared with the per-item calls bitwise for all 64 grids and with the
+oracle on a spread of eight of them.  Tolerance: relative L2 1e-5 (FP32 path).
 """
 import os
 
@@ -15,6 +16,7 @@ import torch
 
 from paper_1404_5756_amd import synth
 from paper_1404_5756_amd.operator import Batch, HorizontalCovariance
+from parity_util import assert_lines
 
 pytestmark = pytest.mark.gpu
 
@@ -45,24 +47,33 @@ def test_c3_forward_and_adjoint_full(orc):
     torch.cuda.synchronize()
     P = _problem(orc, w)
     x64 = xh.astype(np.float64)
-    ef = rel(f.double().cpu().numpy(), P.rf3(x64, threads=THREADS))
-    ea = rel(a.double().cpu().numpy(), P.rf3_adjoint(x64, threads=THREADS))
-    print(f"C3 full: fwd rel L2 {ef:.3e}, adj rel L2 {ea:.3e}", flush=True)
+    fr, ar = P.rf3(x64, threads=THREADS), P.rf3_adjoint(x64, threads=THREADS)
+    fg, ag = f.double().cpu().numpy(), a.double().cpu().numpy()
+    ef, ea = rel(fg, fr), rel(ag, ar)
+    lf, la = assert_lines(fg, fr, "C3 forward"), assert_lines(ag, ar, "C3 adjoint")
+    print(f"C3 full: fwd rel L2 {ef:.3e}, adj rel L2 {ea:.3e}; worst line {lf:.3f} / {la:.3f} of allowance",
+          flush=True)
     assert ef < TOL32 and ea < TOL32
 
 
-def test_c2_forward_full(orc):
+def test_c2_forward_and_adjoint_full(orc):
     dev = torch.device("cuda:0")
     w = synth.c2_regional()
     xh = w.field(np.float32)                       # [2][72][253][871]
     x = torch.from_numpy(xh).to(dev)
     op = _op(w, dev)
     f = op.apply(x)
+    a = op.adjoint(x)
     torch.cuda.synchronize()
     P = _problem(orc, w)
-    e = rel(f.double().cpu().numpy(), P.rf3(xh.astype(np.float64), threads=THREADS))
-    print(f"C2 full: fwd rel L2 {e:.3e}", flush=True)
-    assert e < TOL32
+    x64 = xh.astype(np.float64)
+    fr, ar = P.rf3(x64, threads=THREADS), P.rf3_adjoint(x64, threads=THREADS)
+    fg, ag = f.double().cpu().numpy(), a.double().cpu().numpy()
+    ef, ea = rel(fg, fr), rel(ag, ar)
+    lf, la = assert_lines(fg, fr, "C2 forward"), assert_lines(ag, ar, "C2 adjoint")
+    print(f"C2 full: fwd rel L2 {ef:.3e}, adj rel L2 {ea:.3e}; worst line {lf:.3f} / {la:.3f} of allowance",
+          flush=True)
+    assert ef < TOL32 and ea < TOL32
 
 
 def test_c4_batch_full(orc):
@@ -89,6 +100,7 @@ def test_c4_batch_full(orc):
         ref = _problem(orc, w).rf3(xs[k].double().cpu().numpy(), threads=THREADS)
         e = rel(ys[k].double().cpu().numpy(), ref)
         assert e < TOL32, f"item {k} ({w.name}): {e:.3e}"
+        assert_lines(ys[k].double().cpu().numpy(), ref, f"item {k} ({w.name})")
     b.apply(True)
     torch.cuda.synchronize()
     for k in range(4, len(ws), 8):
@@ -96,3 +108,4 @@ def test_c4_batch_full(orc):
         ref = _problem(orc, w).rf3_adjoint(xs[k].double().cpu().numpy(), threads=THREADS)
         e = rel(ys[k].double().cpu().numpy(), ref)
         assert e < TOL32, f"adjoint item {k} ({w.name}): {e:.3e}"
+        assert_lines(ys[k].double().cpu().numpy(), ref, f"adjoint item {k} ({w.name})")

@@ -143,7 +143,7 @@ def main():
     ap.add_argument("--no-rf1", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-grid batch (C4)")
     ap.add_argument("--no-cg", action="store_true", help="skip the 3D-VAR CG iterations (C5)")
-    ap.add_argument("--cg-iters", type=int, default=10)
+    ap.add_argument("--cg-iters", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); every (field, level) is an "

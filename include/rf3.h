@@ -247,6 +247,22 @@ int rf_dot(rf_prec prec, int64_t n, const void *a, const void *b, void *work, do
            void *stream);
 int rf_cg_q_dot(rf_prec prec, int64_t n, const void *p, const void *w, void *q, void *work, double *s,
                 void *stream);
+
+/* rf_dot without the `work` argument, for callers that cannot allocate device
+ * memory (code under hipGraph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same result, bit for bit, as rf_dot.  The partial sums go
+ * to a fixed scratch array inside the library, rf_dot_noalloc_scratch_bytes()
+ * bytes (8 KiB: one FP64 partial per block of the fixed 1024-block reduction
+ * grid, whatever n), which each GPU the library runs on holds until the process
+ * ends.  Its device address is looked up on the first call on a device (with
+ * that device current).  The call allocates nothing.  All calls on one GPU share
+ * that GPU's scratch: calls that overlap in time on one GPU (different streams
+ * without ordering) race and give wrong sums; calls ordered on a stream do not.
+ * The scratch needs no clearing (every partial is written before it is read).
+ * Errors: as rf_dot; RF_E_HIP if the scratch address cannot be obtained. */
+size_t rf_dot_noalloc_scratch_bytes(void);
+int rf_dot_noalloc(rf_prec prec, int64_t n, const void *a, const void *b, double *s, int32_t slot,
+                   void *stream);
 int rf_cg_step(rf_prec prec, int64_t n, const void *p, const void *q, void *v, void *r, void *work, double *s,
                void *stream);
 int rf_cg_step_pw(rf_prec prec, int64_t n, const void *p, const void *w, void *v, void *r, void *work, double *s,

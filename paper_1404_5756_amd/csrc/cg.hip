@@ -5,6 +5,7 @@
 // deterministic: a fixed grid of blocks writes per-block partial sums (FP64)
 // into the caller's work array, and one block adds them in a fixed order.
 #include <initializer_list>
+#include <mutex>
 
 #include "rf3_internal.h"
 
@@ -246,6 +247,32 @@ bool args_ok(int prec, long n, const void *a, const void *b)
     return (prec == RF_FP32 || prec == RF_FP64) && n >= 1 && a && b;
 }
 
+// Scratch of the allocation-free dot product (rf_dot_noalloc): the per-block
+// FP64 partial sums of the fixed reduction grid.  Every device holds its own
+// copy at its own address; host code never uses the name below as an address,
+// only the pointer hipGetSymbolAddress returns for the current device.
+constexpr int kScratchDoubles = kCgBlocks;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+
+// device address of this device's scratch, looked up once per device (with
+// that device current); null if the lookup fails
+double *scratch_ptr()
+{
+    static std::mutex mu;
+    static double *ptr[kMaxDevices];
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        ptr[dev] = static_cast<double *>(p);
+    }
+    return ptr[dev];
+}
+
 }  // namespace
 
 extern "C" size_t rf_cg_work_bytes(void) { return (size_t)kCgBlocks * sizeof(double); }
@@ -263,6 +290,20 @@ extern "C" int rf_dot(rf_prec prec, int64_t n, const void *a, const void *b, voi
                                                   vec_count(n, 8, {a, b}));
     k_finish<<<1, kCgThreads, 0, st>>>(part, s, slot);
     return hipGetLastError() == hipSuccess ? RF_OK : RF_E_HIP;
+}
+
+extern "C" size_t rf_dot_noalloc_scratch_bytes(void) { return sizeof(scratch); }
+
+extern "C" int rf_dot_noalloc(rf_prec prec, int64_t n, const void *a, const void *b, double *s, int32_t slot,
+                              void *stream)
+{
+    if (!args_ok(prec, n, a, b) || !s || slot < 0 || slot >= RF_CG_SLOTS) return RF_E_ARG;
+    // the reduction grid writes one partial per block: kCgBlocks must fit the scratch
+    static_assert(kCgBlocks <= kScratchDoubles, "scratch smaller than the reduction grid");
+    if (rf_cg_work_bytes() > sizeof(scratch)) return RF_E_UNSUPPORTED;
+    double *part = scratch_ptr();
+    if (!part) return RF_E_HIP;
+    return rf_dot(prec, n, a, b, part, s, slot, stream);
 }
 
 extern "C" int rf_cg_q_dot(rf_prec prec, int64_t n, const void *p, const void *w, void *q, void *work, double *s,

@@ -101,6 +101,10 @@ def lib() -> ctypes.CDLL:
         L64 = ctypes.c_int64
         L.rf_dot.restype = I
         L.rf_dot.argtypes = [I, L64, P, P, P, P, I, P]
+        L.rf_dot_noalloc_scratch_bytes.restype = S
+        L.rf_dot_noalloc_scratch_bytes.argtypes = []
+        L.rf_dot_noalloc.restype = I
+        L.rf_dot_noalloc.argtypes = [I, L64, P, P, P, I, P]
         L.rf_cg_q_dot.restype = I
         L.rf_cg_q_dot.argtypes = [I, L64, P, P, P, P, P, P]
         L.rf_cg_step.restype = I
@@ -273,6 +277,15 @@ def rf_obs_innovation(plan_dev, nobs, nuniq, npts, prec, field, yobs, rinv, scal
 
 def rf_cg_work_bytes() -> int:
     return lib().rf_cg_work_bytes()
+
+
+def rf_dot_noalloc_scratch_bytes() -> int:
+    return lib().rf_dot_noalloc_scratch_bytes()
+
+
+def rf_dot_noalloc(prec, n, a, b, s, slot, stream=None):
+    _check(lib().rf_dot_noalloc(int(prec), int(n), _ptr(a), _ptr(b), _ptr(s), int(slot), _stream(stream)),
+           "rf_dot_noalloc")
 
 
 def rf_dot(prec, n, a, b, work, s, slot, stream=None):

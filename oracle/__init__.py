@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 LITERAL, VARMATCH, FIT = 0, 1, 2
 QMODES = {"literal": LITERAL, "varmatch": VARMATCH, "fit": FIT}
+PERIODIC_X, EXACT_ENDS = 1, 2   # grid flags: zonally periodic rows, exact end conditions of the 3rd-RF
 
 
 def build(force: bool = False) -> str:
@@ -36,7 +37,7 @@ def build(force: bool = False) -> str:
 
 class _Grid(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in
-                ("nx", "ny", "nlev", "mask_nlev", "sigma_nlev", "n_img", "qmode", "k1")]
+                ("nx", "ny", "nlev", "mask_nlev", "sigma_nlev", "n_img", "qmode", "k1", "flags")]
 
 
 _lib = None
@@ -55,6 +56,8 @@ def lib():
         _lib.orc_coef1.argtypes = [i, d, p, p]
         _lib.orc_segments.restype = i
         _lib.orc_segments.argtypes = [p, ctypes.c_long, i, i, p, p, p, p]
+        _lib.orc_segments_cyclic.restype = i
+        _lib.orc_segments_cyclic.argtypes = [p, ctypes.c_long, i, i, p, p, p, p, p]
         for name in ("orc_rf3_apply", "orc_rf3_adjoint"):
             getattr(_lib, name).argtypes = [ctypes.POINTER(_Grid), p, p, p, p, p, i, i, i]
         _lib.orc_rf1_apply.argtypes = [ctypes.POINTER(_Grid), p, p, p, i, p, p, i, i, i]
@@ -110,10 +113,27 @@ def segments(mask_line, n_img):
     return seg, kind, list(zip(st[:nseg].tolist(), en[:nseg].tolist()))
 
 
-class Problem:
-    """Grid description + mask + sigma fields, the arguments the paper states the problem with."""
+def segments_cyclic(mask_line, n_img):
+    """Segments of a periodic line: (seg, kind, [(start, end), ...], whole); a segment may wrap
+    (start > end); whole is True for a line with no land (one cyclic line, no segments)."""
+    m = np.ascontiguousarray(mask_line, dtype=np.uint8)
+    n = m.size
+    seg = np.zeros(n, np.int32)
+    kind = np.zeros(n, np.uint8)
+    st = np.zeros(max(n, 1), np.int32)
+    en = np.zeros(max(n, 1), np.int32)
+    whole = ctypes.c_int(0)
+    nseg = lib().orc_segments_cyclic(_ptr(m), 1, n, int(n_img), _ptr(seg), _ptr(kind), _ptr(st), _ptr(en),
+                                     ctypes.byref(whole))
+    return seg, kind, list(zip(st[:nseg].tolist(), en[:nseg].tolist())), bool(whole.value)
 
-    def __init__(self, mask, sigma_x, sigma_y, n_img=0, qmode=LITERAL, k1=5):
+
+class Problem:
+    """Grid description + mask + sigma fields, the arguments the paper states the problem with.
+    flags: PERIODIC_X (zonally periodic rows) and/or EXACT_ENDS (exact end conditions of the
+    3rd-RF's anti-causal sweep)."""
+
+    def __init__(self, mask, sigma_x, sigma_y, n_img=0, qmode=LITERAL, k1=5, flags=0):
         mask = np.asarray(mask)
         if mask.ndim == 2:
             mask = mask[None]
@@ -128,12 +148,12 @@ class Problem:
         self.sy = np.ascontiguousarray(sy)
         self.ny, self.nx = self.mask.shape[1:]
         assert self.sx.shape[1:] == (self.ny, self.nx) and self.sy.shape == self.sx.shape
-        self.n_img, self.qmode, self.k1 = int(n_img), int(qmode), int(k1)
+        self.n_img, self.qmode, self.k1, self.flags = int(n_img), int(qmode), int(k1), int(flags)
 
     def grid(self, nlev):
         ml, sl = self.mask.shape[0], self.sx.shape[0]
         assert ml in (1, nlev) and sl in (1, nlev), "mask/sigma level count must be 1 or nlev"
-        return _Grid(self.nx, self.ny, nlev, ml, sl, self.n_img, self.qmode, self.k1)
+        return _Grid(self.nx, self.ny, nlev, ml, sl, self.n_img, self.qmode, self.k1, self.flags)
 
     def _prep(self, field):
         f = np.ascontiguousarray(field, dtype=np.float64)

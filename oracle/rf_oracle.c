@@ -440,8 +440,9 @@ typedef struct {
 
 /* Segments of a periodic line (ORC_PERIODIC_X): the same reading as
  * orc_segments with distances taken around the cycle; a land point at equal
- * distance from two runs joins the run before it.  A segment may wrap
- * (starts[r] > ends[r]).  Returns the segment count; 0 with *whole = 1 when
+ * distance from two runs joins the run before it.  A segment is the run's
+ * leading imaginary points (those the run follows), the run, and its trailing
+ * ones (those that follow the run); it may wrap (starts[r] > ends[r]).  Returns the segment count; 0 with *whole = 1 when
  * the line has no land (one cyclic line), 0 with *whole = 0 when it has no sea. */
 int orc_segments_cyclic(const uint8_t *mask, long stride, int n, int n_img,
                         int *seg, uint8_t *kind, int *starts, int *ends, int *whole)
@@ -462,7 +463,11 @@ int orc_segments_cyclic(const uint8_t *mask, long stride, int n, int n_img,
         if (sea && !prev) { starts[nrun] = i; ends[nrun] = i; ++nrun; }
         if (sea) { ends[nrun - 1] = i; seg[i] = nrun - 1; kind[i] = 1; }
     }
+    /* trail[i]: the imaginary point i follows its run (it extends the run's end);
+     * otherwise it precedes the run (it extends the run's start) */
+    uint8_t *trail = malloc(n);
     for (int i = 0; i < n; ++i) {
+        trail[i] = 0;
         if (kind[i] == 1) continue;
         int best = -1, bestd = n_img + 1, best_before = 0;
         for (int r = 0; r < nrun; ++r) {
@@ -472,15 +477,17 @@ int orc_segments_cyclic(const uint8_t *mask, long stride, int n, int n_img,
             int before = dbefore <= dafter;
             if (d < bestd || (d == bestd && before && !best_before)) { bestd = d; best = r; best_before = before; }
         }
-        if (best >= 0 && bestd <= n_img) { seg[i] = best; kind[i] = 2; }
+        if (best >= 0 && bestd <= n_img) { seg[i] = best; kind[i] = 2; trail[i] = (uint8_t)best_before; }
     }
+    /* a segment is its leading imaginary points, the run, its trailing ones */
     for (int r = 0; r < nrun; ++r) {
         int a = starts[r], e = ends[r];
-        while (seg[(a - 1 + n) % n] == r && (a - 1 + n) % n != e) a = (a - 1 + n) % n;
-        while (seg[(e + 1) % n] == r && (e + 1) % n != a) e = (e + 1) % n;
+        while (seg[(a - 1 + n) % n] == r && kind[(a - 1 + n) % n] == 2 && !trail[(a - 1 + n) % n]) a = (a - 1 + n) % n;
+        while (seg[(e + 1) % n] == r && kind[(e + 1) % n] == 2 && trail[(e + 1) % n]) e = (e + 1) % n;
         starts[r] = a;
         ends[r] = e;
     }
+    free(trail);
     return nrun;
 }
 

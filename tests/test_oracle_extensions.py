@@ -130,6 +130,7 @@ def brute_segments_cyclic(mask, n_img):
             if t == e:
                 break
             t = (t + 1) % n
+    trailing = {}
     for i in range(n):
         if mask[i]:
             continue
@@ -137,17 +138,28 @@ def brute_segments_cyclic(mask, n_img):
         for r, (a, e) in enumerate(runs):
             db, da = (i - e) % n, (a - i) % n
             cands.append((min(db, da), 0 if db <= da else 1, r))
-        d, _, r = min(cands)
+        d, side, r = min(cands)
         if d <= n_img:
             owner[i] = r
+            trailing[i] = side == 0
     segs = []
     for r, (a, e) in enumerate(runs):
-        while owner.get((a - 1) % n) == r and (a - 1) % n != e:
+        # leading imaginary points, the run, trailing imaginary points
+        while owner.get((a - 1) % n) == r and trailing.get((a - 1) % n) is False:
             a = (a - 1) % n
-        while owner.get((e + 1) % n) == r and (e + 1) % n != a:
+        while owner.get((e + 1) % n) == r and trailing.get((e + 1) % n) is True:
             e = (e + 1) % n
         segs.append((a, e))
     return sorted(segs), False
+
+
+def test_cyclic_single_run_with_covered_gap(orc):
+    """One run whose land gap is all imaginary points: the segment starts at the first
+    leading point (the gap's second half) and ends at the last trailing one (its first half)."""
+    mask = np.array([1, 1, 1, 0, 0, 0, 0, 1, 1], np.uint8)     # gap 3..6
+    _, kind, segs, whole = orc.segments_cyclic(mask, 2)
+    assert not whole and segs == [(5, 4)]                      # 3, 4 trail the run; 5, 6 lead it
+    assert list(kind) == [1, 1, 1, 2, 2, 2, 2, 1, 1]
 
 
 @pytest.mark.parametrize("n_img", [0, 1, 3])

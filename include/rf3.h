@@ -68,6 +68,25 @@ typedef enum { RF_FP32 = 0, RF_FP64 = 1 } rf_prec;
  *             distance of the impulse response to exp(-x^2/(2 sigma^2)). */
 typedef enum { RF_Q_LITERAL = 0, RF_Q_VARMATCH = 1, RF_Q_FIT = 2 } rf_qmode;
 
+/* Options beyond the paper's scheme (rf_grid.flags, a bitwise or; 0 = the paper):
+ *   RF_PERIODIC_X: rows are zonally periodic (global grids; the paper treats
+ *     finite lines).  Sea runs and imaginary points are found around each row
+ *     (a run may wrap from x = nx-1 to x = 0; a land point at equal distance
+ *     from two runs joins the run before it).  A row with no land is one
+ *     cyclic line: its recurrences take their periodic solution, the fixed
+ *     point of one lap (a 3x3 solve per line).  Columns are never periodic.
+ *   RF_EXACT_ENDS: end conditions of the 3rd-RF at coasts and line ends
+ *     (Sec. 6 names other boundary conditions at the coasts as further work).
+ *     The anti-causal sweep of each segment starts from the three values the
+ *     infinite-line filter carries back from past the segment end (input zero
+ *     outside the segment, the last point's coefficients continued), a 3x3
+ *     matrix of the last three causal values computed in FP64 at setup; each
+ *     segment's operator is then the infinite-line filter restricted to it
+ *     (for uniform sigma a Toeplitz matrix, equally damped at both ends).
+ *     The zero start of the causal sweep is already exact.  The 1st-RF keeps
+ *     the paper's zero ends. */
+enum { RF_PERIODIC_X = 1, RF_EXACT_ENDS = 2 };
+
 typedef struct {
     int32_t nx, ny, nlev;   /* one level is [ny][nx], x fastest; 1 <= nx, ny <= 65535, nlev >= 1 */
     int32_t mask_nlev;      /* 1 (one 2-D mask for every level) or nlev */
@@ -75,6 +94,7 @@ typedef struct {
     int32_t n_img;          /* imaginary sea points per coast, 0 <= n_img <= 64 */
     int32_t qmode;          /* rf_qmode */
     int32_t k1;             /* iteration count K the 1st-RF coefficients are built for (E = K/sigma^2), >= 1 */
+    int32_t flags;          /* RF_PERIODIC_X | RF_EXACT_ENDS, or 0 */
 } rf_grid;
 
 /* Size in bytes of the coefficient block rf_coeffs fills for grid g (0 if g is

@@ -11,7 +11,7 @@ using namespace rf;
 
 namespace {
 
-LineGeom geom(const rf_grid *g, int dir, int nlev, int nfields)
+LineGeom geom(const rf_grid *g, int dir, int nlev, int nfields, const void *coef)
 {
     LineGeom G;
     G.n = dir == 0 ? g->nx : g->ny;
@@ -23,6 +23,12 @@ LineGeom geom(const rf_grid *g, int dir, int nlev, int nfields)
     G.nlev = nlev;
     G.mask_per_lev = g->mask_nlev > 1;
     G.coef_per_lev = g->sigma_nlev > 1;
+    G.periodic = dir == 0 && (g->flags & RF_PERIODIC_X);
+    G.per = nullptr;
+    if (G.periodic) {
+        const BlockHeader h = layout(g);
+        G.per = reinterpret_cast<const double *>(reinterpret_cast<const char *>(coef) + h.off_perseq);
+    }
     return G;
 }
 
@@ -75,8 +81,9 @@ static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void
     const bool tiled2d = g->mask_nlev == 1 && g->sigma_nlev == 1 && !force_sequential();
     const int nplanes = nlev * nfields;
     if (tiled2d && dir == 0 && h.lx) {
+        const float *pert = h.off_perx ? tab<float>(coef, h.off_perx) : nullptr;
         hipError_t e = fast_rf3_x(in, out, tab<float4>(coef, h.off_f32[0]), tab<uint64_t>(coef, h.off_lmx),
-                                  tab<float>(coef, h.off_phix), h.lx, g->nx, g->ny, nplanes, adj, st);
+                                  tab<float>(coef, h.off_phix), h.lx, g->nx, g->ny, nplanes, adj, pert, st);
         if (e != hipErrorNotSupported) return e;
     }
     if (tiled2d && dir == 1 && h.ly) {
@@ -85,7 +92,7 @@ static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void
                                   nplanes, adj, st);
         if (e != hipErrorNotSupported) return e;
     }
-    const LineGeom G = geom(g, dir, nlev, nfields);
+    const LineGeom G = geom(g, dir, nlev, nfields, coef);
     const float4 *T1 = tab<float4>(coef, adj ? h.off_a32[dir] : h.off_f32[dir]);
     const float4 *T2 = tab<float4>(coef, adj ? h.off_d32[dir] : h.off_f32[dir]);
     return seq_rf3_f32(in, out, T1, T2, tab<uint8_t>(coef, h.off_code[dir]), G, adj, st);
@@ -97,7 +104,7 @@ static hipError_t rf3_dir(const rf_grid *g, const BlockHeader &h, const void *co
     if (prec == RF_FP32)
         return rf3_dir_f32(g, h, coef, dir, adj, (const float *)in, (float *)out, nlev, nfields, st);
     return seq_rf3_f64((const double *)in, (double *)out, tab<double4>(coef, h.off_f64[dir]),
-                       tab<uint8_t>(coef, h.off_code[dir]), geom(g, dir, nlev, nfields), adj, st);
+                       tab<uint8_t>(coef, h.off_code[dir]), geom(g, dir, nlev, nfields, coef), adj, st);
 }
 
 int rf::rf3_run(const rf_grid *g, const void *coef, rf_prec prec, const void *in, void *out,
@@ -149,7 +156,7 @@ extern "C" int rf1_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, in
     const BlockHeader h = layout(g);
     hipError_t e = hipSuccess;
     for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
-        const LineGeom G = geom(g, dir, nlev, nfields);
+        const LineGeom G = geom(g, dir, nlev, nfields, coef);
         const double2 *C = tab<double2>(coef, h.off_r1[dir]);
         const uint8_t *code = tab<uint8_t>(coef, h.off_code[dir]);
         for (int k = 0; k < K && e == hipSuccess; ++k) {

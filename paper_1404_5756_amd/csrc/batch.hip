@@ -3,7 +3,8 @@
 // and y column blocks, run by one work-list launch per occupancy class of the
 // x tile sizes and one for all y units.  The work list ("plan") is built on the host from the items and
 // the block layout alone; the caller copies it to device memory once.  Items
-// whose mask or sigma vary with level run the line-sequential path.
+// whose mask or sigma vary with level, and items with periodic rows or exact
+// ends, are applied one by one (rf3_run).
 #include <algorithm>
 #include <map>
 #include <string.h>
@@ -17,7 +18,7 @@ using namespace rf;
 namespace {
 
 constexpr uint32_t kPlanMagic = 0x50424652u;   // "RFBP"
-constexpr uint32_t kPlanVersion = 2;
+constexpr uint32_t kPlanVersion = 3;
 // default planes per y work unit: the unit's setup (transfer matrices into
 // LDS) is shared by this many planes of its column block
 constexpr int kYPlanesPerUnit = 8;
@@ -103,7 +104,8 @@ int build(const rf_batch_item *items, int32_t n, const rf_batch_tuning *tuning, 
         e.nx = g->nx;
         e.ny = g->ny;
         e.nplanes = (int32_t)nplanes;
-        const bool tiled = !seq_all && g->mask_nlev == 1 && g->sigma_nlev == 1 && h.lx && h.ly &&
+        // periodic rows and exact ends: the per-item path (rf3_run) runs their own kernels
+        const bool tiled = !seq_all && g->flags == 0 && g->mask_nlev == 1 && g->sigma_nlev == 1 && h.lx && h.ly &&
                            (long)g->nx * g->ny * 16 < (1L << 31);
         if (!tiled) {
             P.seq_items.push_back(i);

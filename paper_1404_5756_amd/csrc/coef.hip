@@ -63,22 +63,24 @@ __device__ inline Coef3 coef3(int mode, double sigma)
 }
 
 // kind of point i of a line: 0 outside every segment, 1 sea, 2 imaginary point
-// of the run before it, 3 imaginary point of the run after it.
-__device__ inline int classify(const uint8_t *m, long es, int n, int i, int n_img)
+// of the run before it, 3 imaginary point of the run after it.  On a periodic
+// line (per) the neighbours are taken around the cycle.
+__device__ inline int classify(const uint8_t *m, long es, int n, int i, int n_img, bool per)
 {
     if (m[(long)i * es]) return 1;
     int dl = n_img + 1, dr = n_img + 1;
-    for (int k = 1; k <= n_img && i - k >= 0; ++k)
-        if (m[(long)(i - k) * es]) { dl = k; break; }
-    for (int k = 1; k <= n_img && i + k < n; ++k)
-        if (m[(long)(i + k) * es]) { dr = k; break; }
+    for (int k = 1; k <= n_img && (per || i - k >= 0); ++k)
+        if (m[(long)(((i - k) % n + n) % n) * es]) { dl = k; break; }
+    for (int k = 1; k <= n_img && (per || i + k < n); ++k)
+        if (m[(long)((i + k) % n) * es]) { dr = k; break; }
     if (dl > n_img && dr > n_img) return 0;
     return dl <= dr ? 2 : 3;
 }
 
-// One thread per (mask level, y, x); writes the codes of both directions.
+// One thread per (mask level, y, x); writes the codes of both directions
+// (rows periodic when periodic_x).
 __global__ void k_seg(const uint8_t *__restrict__ mask, uint8_t *__restrict__ code_x,
-                      uint8_t *__restrict__ code_y, int nx, int ny, int nl, int n_img)
+                      uint8_t *__restrict__ code_y, int nx, int ny, int nl, int n_img, int periodic_x)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long plane = (long)nx * ny;
@@ -91,19 +93,22 @@ __global__ void k_seg(const uint8_t *__restrict__ mask, uint8_t *__restrict__ co
         const int n = d == 0 ? nx : ny;
         const int i = d == 0 ? x : y;
         const long es = d == 0 ? 1 : nx;
+        const bool per = d == 0 && periodic_x;
         const uint8_t *line = d == 0 ? mp + (long)y * nx : mp + x;
-        const int k = classify(line, es, n, i, n_img);
-        const int kp = i > 0 ? classify(line, es, n, i - 1, n_img) : 0;
-        const int kn = i < n - 1 ? classify(line, es, n, i + 1, n_img) : 0;
+        const int k = classify(line, es, n, i, n_img, per);
+        const bool first = !per && i == 0, last = !per && i == n - 1;
+        const int kp = first ? 0 : classify(line, es, n, (i - 1 + n) % n, n_img, per);
+        const int kn = last ? 0 : classify(line, es, n, (i + 1) % n, n_img, per);
         uint8_t c = 0;
         if (k == 1) c |= CODE_SEA;
         if (k != 0) {
             c |= CODE_ACTIVE;
             // a new segment starts where the previous point is outside every
             // segment or is an imaginary point of the run before a gap whose
-            // other side (this point) belongs to the next run
-            const bool start = (i == 0) || kp == 0 || (kp == 2 && (k == 3 || k == 1));
-            const bool end = (i == n - 1) || kn == 0 || (k == 2 && (kn == 3 || kn == 1));
+            // other side (this point) belongs to the next run (on a periodic
+            // row with no land there is neither a start nor an end)
+            const bool start = first || kp == 0 || (kp == 2 && (k == 3 || k == 1));
+            const bool end = last || kn == 0 || (k == 2 && (kn == 3 || kn == 1));
             if (start) c |= CODE_FRESET;
             if (end) c |= CODE_BRESET;
         } else {
@@ -114,10 +119,12 @@ __global__ void k_seg(const uint8_t *__restrict__ mask, uint8_t *__restrict__ co
 }
 
 // alpha_{., k} of the point `off` steps away along the line, 0 outside the line
-// or where sigma is not usable (such points never reach a used state term).
-__device__ inline double alpha_at(const double *sig, long es, int n, int i, int off, int k, int mode)
+// or where sigma is not usable (such points never reach a used state term); on
+// a periodic line the point is taken around the cycle.
+__device__ inline double alpha_at(const double *sig, long es, int n, int i, int off, int k, int mode, bool per)
 {
-    const int j = i + off;
+    int j = i + off;
+    if (per) j = ((j % n) + n) % n;
     if (j < 0 || j >= n) return 0.0;
     const double s = sig[(long)j * es];
     if (!sigma_ok(s)) return 0.0;
@@ -162,13 +169,14 @@ __global__ void k_coef(const double *__restrict__ sx, const double *__restrict__
             const int n = d == 0 ? nx : ny, i = d == 0 ? x : y;
             const long es = d == 0 ? 1 : nx;
             const double *line = d == 0 ? sig + (long)y * nx : sig + x;
-            const double A1 = alpha_at(line, es, n, i, -1, 1, mode);
-            const double A2 = alpha_at(line, es, n, i, -2, 2, mode);
-            const double A3 = alpha_at(line, es, n, i, -3, 3, mode);
+            const bool per = d == 0 && (h.g.flags & RF_PERIODIC_X);
+            const double A1 = alpha_at(line, es, n, i, -1, 1, mode, per);
+            const double A2 = alpha_at(line, es, n, i, -2, 2, mode, per);
+            const double A3 = alpha_at(line, es, n, i, -3, 3, mode, per);
             a = make_float4((float)c.beta_g, (float)(1.0 - A1 - A2 - A3), (float)(A2 + A3), (float)A3);
-            const double D1 = alpha_at(line, es, n, i, 1, 1, mode);
-            const double D2 = alpha_at(line, es, n, i, 2, 2, mode);
-            const double D3 = alpha_at(line, es, n, i, 3, 3, mode);
+            const double D1 = alpha_at(line, es, n, i, 1, 1, mode, per);
+            const double D2 = alpha_at(line, es, n, i, 2, 2, mode, per);
+            const double D3 = alpha_at(line, es, n, i, 3, 3, mode, per);
             b = make_float4((float)c.beta_g, (float)(1.0 - D1 - D2 - D3), (float)(D2 + D3), (float)D3);
             const double E = (double)h.g.k1 / (s * s);
             const double rt = sqrt(E * (E + 2.0));
@@ -239,6 +247,74 @@ __global__ void k_lanemask_y(const uint8_t *__restrict__ code, uint64_t *__restr
     o[2 * lys] = ~s;
 }
 
+// ---- periodic rows: one-lap fixed points of the line-sequential kernels
+__device__ inline void m3_mul(const double *A, const double *B, double *C)   // C = A B
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+// W = (I - Phi)^-1 by the adjugate (Phi: a stable lap, I - Phi well away from singular)
+__device__ inline void m3_inv_i_minus(const double *Phi, double *W)
+{
+    double A[9];
+    for (int e = 0; e < 9; ++e) A[e] = (e % 4 == 0 ? 1.0 : 0.0) - Phi[e];
+    const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+    const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    W[0] = c00 / det; W[1] = (A[2] * A[7] - A[1] * A[8]) / det; W[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    W[3] = c01 / det; W[4] = (A[0] * A[8] - A[2] * A[6]) / det; W[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    W[6] = c02 / det; W[7] = (A[1] * A[6] - A[0] * A[7]) / det; W[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+}
+
+// One thread per (sigma level, row).  For a periodic row with no land the
+// sequential kernels run one lap from a zero state (ending in b), start the
+// real lap from the fixed point W b, W = (I - Phi_lap)^-1.  Laps of the four
+// sweeps (forward ascending/descending, adjoint ascending/descending), in the
+// printed form (state: the last three values; step matrix rows
+// (a1, a2, a3), (1, 0, 0), (0, 1, 0) with the adjoint's source-indexed alphas)
+// and in the FP32 increment form (state (p, d1, d2), step matrix
+// (1-g, -c2, -c3), (-g, -c2, -c3), (0, 1, 0) with the kernel's FP32 table),
+// and the 1st-RF's scalar lap prod(alpha).
+__global__ void k_perseq(const char *__restrict__ blk, double *__restrict__ out, BlockHeader h)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = h.g.nx, ny = h.g.ny;
+    if (t >= (long)h.g.sigma_nlev * ny) return;
+    const long base = t * nx;   // (level * ny + row) * nx
+    const double4 *C = reinterpret_cast<const double4 *>(blk + h.off_f64[0]) + base;
+    const float4 *T[3] = {reinterpret_cast<const float4 *>(blk + h.off_f32[0]) + base,
+                          reinterpret_cast<const float4 *>(blk + h.off_a32[0]) + base,
+                          reinterpret_cast<const float4 *>(blk + h.off_d32[0]) + base};
+    const double2 *R1 = reinterpret_cast<const double2 *>(blk + h.off_r1[0]) + base;
+    double *o = out + t * kPerSeq;
+    auto wrap = [&](int i) { return ((i % nx) + nx) % nx; };
+    for (int kind = 0; kind < 4; ++kind) {
+        const bool desc = kind & 1;
+        double Pd[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, Pf[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, N[9];
+        const float4 *Tk = T[kind == 0 || kind == 1 ? 0 : kind - 1];
+        for (int s = 0; s < nx; ++s) {
+            const int i = desc ? nx - 1 - s : s;
+            double a1, a2, a3;
+            if (kind < 2) { a1 = C[i].y; a2 = C[i].z; a3 = C[i].w; }
+            else if (kind == 2) { a1 = C[wrap(i - 1)].y; a2 = C[wrap(i - 2)].z; a3 = C[wrap(i - 3)].w; }
+            else { a1 = C[wrap(i + 1)].y; a2 = C[wrap(i + 2)].z; a3 = C[wrap(i + 3)].w; }
+            const double Md[9] = {a1, a2, a3, 1, 0, 0, 0, 1, 0};
+            m3_mul(Md, Pd, N);
+            for (int e = 0; e < 9; ++e) Pd[e] = N[e];
+            const float4 k = Tk[i];
+            const double g = k.y, c2 = k.z, c3 = k.w;
+            const double Mf[9] = {1 - g, -c2, -c3, -g, -c2, -c3, 0, 1, 0};
+            m3_mul(Mf, Pf, N);
+            for (int e = 0; e < 9; ++e) Pf[e] = N[e];
+        }
+        m3_inv_i_minus(Pd, o + 9 * kind);
+        m3_inv_i_minus(Pf, o + kPerSeqDelta + 9 * kind);
+    }
+    double prod = 1.0;
+    for (int i = 0; i < nx; ++i) prod *= R1[i].x;
+    o[kPerSeqRf1] = o[kPerSeqRf1 + 1] = 1.0 / (1.0 - prod);
+    o[kPerSeqRf1 + 2] = o[kPerSeqRf1 + 3] = 0.0;
+}
+
 bool grid_ok(const rf_grid *g)
 {
     if (!g) return false;
@@ -248,6 +324,7 @@ bool grid_ok(const rf_grid *g)
     if (g->n_img < 0 || g->n_img > 64) return false;
     if (g->qmode < RF_Q_LITERAL || g->qmode > RF_Q_FIT) return false;
     if (g->k1 < 1) return false;
+    if (g->flags & ~(RF_PERIODIC_X | RF_EXACT_ENDS)) return false;
     return true;
 }
 
@@ -260,7 +337,7 @@ BlockHeader layout(const rf_grid *g)
     const size_t plane = (size_t)g->nx * g->ny;
     h.npts_c = plane * g->sigma_nlev;
     h.npts_m = plane * g->mask_nlev;
-    size_t off = 256;
+    size_t off = kHeaderBytes;
     for (int d = 0; d < 2; ++d) {
         h.off_f32[d] = off; off = align256(off + 16 * h.npts_c);
         h.off_a32[d] = off; off = align256(off + 16 * h.npts_c);
@@ -282,6 +359,26 @@ BlockHeader layout(const rf_grid *g)
     if (h.lx && g->mask_nlev == 1 && g->sigma_nlev == 1) off = align256(off + (size_t)g->ny * 4 * 64 * 12 * 4);
     h.off_ky = off;
     if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1) off = align256(off + (size_t)4 * plane * 3 * 4);
+    const bool tiled2d = g->mask_nlev == 1 && g->sigma_nlev == 1;
+    h.off_perx = h.off_perseq = 0;
+    if (g->flags & RF_PERIODIC_X) {
+        if (h.lx && tiled2d) { h.off_perx = off; off = align256(off + (size_t)g->ny * 4 * kPerXEntries * 12 * 4); }
+        h.off_perseq = off;
+        off = align256(off + (size_t)g->sigma_nlev * g->ny * kPerSeq * 8);
+    }
+    h.end_nlev = 0;
+    for (int d = 0; d < 2; ++d) h.off_endd[d] = h.off_endf[d] = 0;
+    if (g->flags & RF_EXACT_ENDS) {
+        h.end_nlev = g->mask_nlev > g->sigma_nlev ? g->mask_nlev : g->sigma_nlev;
+        for (int d = 0; d < 2; ++d) {
+            h.off_endd[d] = off;
+            off = align256(off + (size_t)h.end_nlev * plane * 2 * 9 * 8);
+            if (tiled2d && (d == 0 ? h.lx : h.ly)) {
+                h.off_endf[d] = off;
+                off = align256(off + plane * 2 * 12 * 4);
+            }
+        }
+    }
     h.total_bytes = off;
     return h;
 }
@@ -309,7 +406,7 @@ extern "C" int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *si
     const long nm = (long)h.npts_m, nc = (long)h.npts_c;
     k_seg<<<(unsigned)((nm + 255) / 256), 256, 0, st>>>(mask, (uint8_t *)(blk + h.off_code[0]),
                                                       (uint8_t *)(blk + h.off_code[1]), g->nx, g->ny,
-                                                      g->mask_nlev, g->n_img);
+                                                      g->mask_nlev, g->n_img, (g->flags & RF_PERIODIC_X) != 0);
     if (hipGetLastError() != hipSuccess) return RF_E_HIP;
     k_coef<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(sigma_x, sigma_y, (const uint8_t *)(blk + h.off_code[0]),
                                                        (const uint8_t *)(blk + h.off_code[1]), blk, h);
@@ -340,6 +437,16 @@ extern "C" int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *si
         if (setup_ky_y((const float4 *)(blk + h.off_f32[1]), (const uint8_t *)(blk + h.off_code[1]),
                        (float *)(blk + h.off_ky), g->nx, g->ny, h.ly, st) != hipSuccess)
             return RF_E_HIP;
+    }
+    if (h.off_perx) {
+        if (setup_per_x((const float4 *)(blk + h.off_f32[0]), (const uint8_t *)(blk + h.off_code[0]),
+                        (float *)(blk + h.off_perx), g->nx, g->ny, h.lx, st) != hipSuccess)
+            return RF_E_HIP;
+    }
+    if (h.off_perseq) {
+        const long n = (long)g->sigma_nlev * g->ny;
+        k_perseq<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(blk, (double *)(blk + h.off_perseq), h);
+        if (hipGetLastError() != hipSuccess) return RF_E_HIP;
     }
     int32_t err = 0;
     if (hipMemcpyAsync(&err, blk + offsetof(BlockHeader, sigma_error), sizeof(err), hipMemcpyDeviceToHost, st) != hipSuccess)

@@ -10,7 +10,8 @@
 namespace rf {
 
 constexpr uint32_t kMagic = 0x52463321u;   // "RF3!"
-constexpr uint32_t kVersion = 3;
+constexpr uint32_t kVersion = 4;
+constexpr size_t kHeaderBytes = 512;         // the tables start here
 
 // Per-point coast code bits (one byte per point and direction).
 enum : uint8_t {
@@ -52,8 +53,33 @@ struct BlockHeader {
     uint64_t off_phiy;        // float [nblk][4][16][64][12]: y-chunk transfer matrices (2-D mask and sigma only)
     uint64_t off_phix;        // float [ny][4][64][12]: x-chunk transfer matrices (2-D mask and sigma only)
     uint64_t off_ky;          // float [4][ny][nx][3]: y local-pass K vectors (2-D mask and sigma only)
+    // RF_PERIODIC_X (0 otherwise):
+    uint64_t off_perx;        // float [ny][4][kPerXEntries][12]: cyclic scan of the tiled x kernel (2-D only)
+    uint64_t off_perseq;      // double [sigma_nlev][ny][kPerSeq]: one-lap fixed points of the sequential kernels
+    // RF_EXACT_ENDS (0 otherwise): 3x3 end matrices at segment ends, zero elsewhere
+    uint64_t off_endd[2];     // double [end_nlev][ny][nx][2][9]: forward J M, adjoint M^T J^T (on p and z)
+    uint64_t off_endf[2];     // float [ny][nx][2][12]: the same times diag(1/beta) (tiled kernels, 2-D only)
+    int32_t end_nlev;         // max(mask_nlev, sigma_nlev) when RF_EXACT_ENDS
+    int32_t pad2;
 };
-static_assert(sizeof(BlockHeader) <= 256, "header must fit in 256 bytes");
+static_assert(sizeof(BlockHeader) <= kHeaderBytes, "header must fit before the tables");
+
+// Cyclic scan of the tiled x kernel on periodic rows, per row and kind
+// (0 forward ascending, 1 forward descending, 2 adjoint ascending, 3 adjoint
+// descending), 12 floats (a row-major 3x3, padded) per entry:
+//   entries 0..63: P_c, the transfer from the wrap state to the state entering
+//     chunk c (ascending: Phi_{c-1}..Phi_0; descending: Phi_{c+1}..Phi_{c_last}
+//     with the last real chunk c_last taken from its last real point on);
+//   entry 64: W = (I - Phi_lap)^-1 (Phi_lap: one lap of the row's real points);
+//   entry 65: ascending kinds, the transfer of chunk c_last up to the row's
+//     last point (its steps past nx are padding).
+constexpr int kPerXEntries = 66;
+// One-lap fixed points of the line-sequential kernels on periodic rows, per
+// (sigma level, row), doubles: W = (I - Phi_lap)^-1 for the FP64 printed form
+// (4 kinds x 9), for the FP32 increment form (4 kinds x 9), and the 1st-RF's
+// scalar 1 / (1 - prod alpha) (ascending, descending); padded to 76.
+constexpr int kPerSeq = 76;
+constexpr int kPerSeqDelta = 36, kPerSeqRf1 = 72;
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -97,6 +123,8 @@ struct BatchEntry {
     const float *KY;
     const uint64_t *LM[2];
     const float *PHI[2];
+    const float *PER;         // cyclic x scan tables (periodic rows), or null
+    const float *END[2];      // exact-end tables of the tiled kernels, or null
     int32_t nx, ny, nplanes, pad;
 };
 struct BatchUnit {
@@ -114,6 +142,8 @@ struct LineGeom {
     int nlev;         // levels per field (plane index % nlev = level)
     int mask_per_lev; // 1: code tables have one plane per level; 0: a single 2-D plane
     int coef_per_lev; // same for coefficient tables
+    int periodic;     // lines are cycles (periodic rows)
+    const double *per;// periodic: one-lap fixed points [coefficient level][line][kPerSeq]
 };
 
 __host__ __device__ inline long plane_offset(const LineGeom &G, int pl, int per_lev)

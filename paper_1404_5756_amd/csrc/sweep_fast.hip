@@ -172,8 +172,11 @@ struct XRow {
     // MODE 2: input v, output written back into v.  Forward inputs are beta_i s_i
     // (formed once for both passes), and the forward output is beta_i u_i, the
     // input of the anti-causal passes.
-    template <int MODE>
-    __device__ __forceinline__ void asc(St &x, float *v) const
+    // PER (periodic rows): `save` receives the state after step s_hook (the
+    // row's last point, in the last real chunk), and desc sets the state of lane
+    // `inj_lane` to `inj` before step s_hook.
+    template <int MODE, bool PER = false>
+    __device__ __forceinline__ void asc(St &x, float *v, int s_hook = 0, St *save = nullptr) const
     {
         // forward: zero the state before a segment start; adjoint: after a segment end.
         // The opaque zero keeps this pass's mask loads inside the pass.
@@ -190,11 +193,13 @@ struct XRow {
                 st_reset(x, m);
                 if (MODE == 2) v[i] = o;
             }
+            if (PER && i == s_hook) *save = x;
         }
     }
     // descending sweep over my chunk; MODE 2 also applies the sea mask to the output
-    template <int MODE>
-    __device__ __forceinline__ void desc(St &x, float *v) const
+    template <int MODE, bool PER = false>
+    __device__ __forceinline__ void desc(St &x, float *v, int s_hook = 0, bool inj_lane = false,
+                                         St inj = St{0.f, 0.f, 0.f}) const
     {
         // forward: zero the state before a segment end; adjoint: after a segment start
         const int z = fresh_int(0);
@@ -203,6 +208,11 @@ struct XRow {
 #pragma unroll
         for (int i = L - 1; i >= 0; --i) {
             const uint64_t m = rp[i];
+            if (PER && i == s_hook) {
+                x.a = inj_lane ? inj.a : x.a;
+                x.b = inj_lane ? inj.b : x.b;
+                x.c = inj_lane ? inj.c : x.c;
+            }
             if (!ADJ) {
                 st_reset(x, m);
                 fwd_step(x, v[i], kg[i], k2[i], k3[i]);
@@ -302,9 +312,11 @@ __device__ __forceinline__ void ks_round(const float *k, const St &x, St &y)
     mat_acc(A, x, y);
 }
 
-// b: local end state of my chunk; returns the state entering my chunk
+// b: local end state of my chunk; returns the state entering my chunk.  With
+// incl0, the descending scan also returns the state leaving chunk 0 (lane 0's
+// inclusive value).
 template <bool DESC>
-__device__ __forceinline__ St ks_carry(St b, const float *K, int lane)
+__device__ __forceinline__ St ks_carry(St b, const float *K, int lane, St *incl0 = nullptr)
 {
     const float *k = K + lane * kKs;
     if (!DESC) {
@@ -326,7 +338,18 @@ __device__ __forceinline__ St ks_carry(St b, const float *K, int lane)
                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.b), 32)),
                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.c), 32))};
     ks_round(k + 45, u, b);
+    if (incl0)
+        *incl0 = St{__int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.a), 0)),
+                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.b), 0)),
+                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b.c), 0))};
     return st_dpp<DPP_WAVE_SHL1, 0xF>(b);
+}
+
+// a wave-uniform 3x3 (row-major, 12-float entry) of a read-only table
+__device__ __forceinline__ void load_m3(const float *p, float *A)
+{
+#pragma unroll
+    for (int e = 0; e < 9; ++e) A[e] = p[e];
 }
 
 template <int L>
@@ -334,10 +357,10 @@ constexpr int x_stage_floats() { return 256 * ((L + 3) / 4); }   // whole dwordx
 
 // Lines of one row: planes grp, grp + groups, ... (4 waves, interleaved).
 // K: [2][64 * kKs] scan matrices, stage: this wave's LDS staging area.
-template <int L, bool ADJ>
+template <int L, bool ADJ, bool PER = false>
 __device__ __forceinline__ void x_rows(const float *in, float *out, const float4 *T, const uint64_t *LM,
                                        const float *PHI, int nx, int ny, int nplanes, int row, int grp,
-                                       int groups, float *K, float *stg)
+                                       int groups, float *K, float *stg, const float *PERT = nullptr)
 {
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long plane = (long)nx * ny;
@@ -400,13 +423,56 @@ __device__ __forceinline__ void x_rows(const float *in, float *out, const float4
             }
         }
         St x{0.f, 0.f, 0.f};
-        R.template asc<1>(x, v);
-        x = ks_carry<false>(x, K, lane);
-        R.template asc<2>(x, v);
-        St y{0.f, 0.f, 0.f};
-        R.template desc<1>(y, v);
-        y = ks_carry<true>(y, K + 64 * kKs, lane);
-        R.template desc<2>(y, v);
+        if (!PER) {
+            R.template asc<1>(x, v);
+            x = ks_carry<false>(x, K, lane);
+            R.template asc<2>(x, v);
+            St y{0.f, 0.f, 0.f};
+            R.template desc<1>(y, v);
+            y = ks_carry<true>(y, K + 64 * kKs, lane);
+            R.template desc<2>(y, v);
+        } else {
+            // periodic row: the carry scans are cyclic.  Ascending: the state after
+            // the row's last point (x = nx-1, step s_last of chunk c_last) with a zero
+            // state entering x = 0 is Phi_last carry(c_last) + (its local state); the
+            // state entering x = 0 is the fixed point x0 = W that, and every chunk's
+            // carry gains P_c x0.  Descending: mirrored, from the state leaving chunk
+            // 0, with lane c_last's state set at its last real point.
+            const int clast = (nx - 1) / L, slast = (nx - 1) % L;
+            const float *pa = PERT + ((long)row * 4 + (ADJ ? 2 : 0)) * kPerXEntries * 12;
+            const float *pd = PERT + ((long)row * 4 + (ADJ ? 3 : 1)) * kPerXEntries * 12;
+            St saved{0.f, 0.f, 0.f};
+            R.template asc<1, true>(x, v, slast, &saved);
+            x = ks_carry<false>(x, K, lane);
+            {
+                float A[9];
+                load_m3(pa + 65 * 12, A);
+                St bw = saved;
+                mat_acc(A, x, bw);
+                const St b{__int_as_float(__builtin_amdgcn_readlane(__float_as_int(bw.a), clast)),
+                           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bw.b), clast)),
+                           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bw.c), clast))};
+                load_m3(pa + 64 * 12, A);
+                St x0{0.f, 0.f, 0.f};
+                mat_acc(A, b, x0);
+                load_m3(pa + lane * 12, A);
+                mat_acc(A, x0, x);
+            }
+            R.template asc<2>(x, v);
+            St y{0.f, 0.f, 0.f};
+            R.template desc<1>(y, v);
+            St out0;
+            y = ks_carry<true>(y, K + 64 * kKs, lane, &out0);
+            St xw{0.f, 0.f, 0.f};
+            {
+                float A[9];
+                load_m3(pd + 64 * 12, A);
+                mat_acc(A, out0, xw);
+                load_m3(pd + lane * 12, A);
+                mat_acc(A, xw, y);
+            }
+            R.template desc<2, true>(y, v, slast, lane == clast, xw);
+        }
         // chunk-major into LDS, out in coalesced dwordx4 rounds
 #pragma unroll
         for (int i = 0; i < L; ++i) stg[x0 + i] = v[i];
@@ -429,10 +495,10 @@ __device__ __forceinline__ void x_rows(const float *in, float *out, const float4
     }
 }
 
-template <int L, bool ADJ>
+template <int L, bool ADJ, bool PER>
 __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
     const float *in, float *out, const float4 *__restrict__ T, const uint64_t *__restrict__ LM,
-    const float *__restrict__ PHI, int nx, int ny, int nplanes, int groups)
+    const float *__restrict__ PHI, int nx, int ny, int nplanes, int groups, const float *__restrict__ PERT)
 {
     __shared__ float K[2 * 64 * kKs];
     __shared__ __align__(16) float stage[kXWaves][x_stage_floats<L>()];
@@ -441,8 +507,8 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
     const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
     const int row = (slot / groups) * 8 + xcd, grp = slot % groups;
     if (row >= ny) return;
-    x_rows<L, ADJ>(in, out, T, LM, PHI, nx, ny, nplanes, row, grp, groups, K,
-                   stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+    x_rows<L, ADJ, PER>(in, out, T, LM, PHI, nx, ny, nplanes, row, grp, groups, K,
+                        stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)], PERT);
 }
 
 // Batched form: one workgroup per work unit {item, row, group, groups}; the
@@ -797,11 +863,10 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_batch(const BatchEntry
 // (2) / start (3).  cf(i), cd(i): coefficients and code of chunk point i
 // (ascending position).
 template <class CF, class CD>
-__device__ void chunk_transfer(int kind, int n, CF cf, CD cd, float *dst)
+__device__ void chunk_transfer_d(int kind, int n, CF cf, CD cd, double *A)
 {
     const bool desc = kind & 1;
     const uint8_t flag = kind == 0 ? CODE_FRESET : kind == 1 ? CODE_BRESET : kind == 2 ? CODE_BRESET : CODE_FRESET;
-    double A[9];
     for (int k = 0; k < 3; ++k) {
         double s0 = k == 0, s1 = k == 1, s2 = k == 2;
         for (int ii = 0; ii < n; ++ii) {
@@ -828,6 +893,12 @@ __device__ void chunk_transfer(int kind, int n, CF cf, CD cd, float *dst)
         A[3 + k] = s1;
         A[6 + k] = s2;
     }
+}
+template <class CF, class CD>
+__device__ void chunk_transfer(int kind, int n, CF cf, CD cd, float *dst)
+{
+    double A[9];
+    chunk_transfer_d(kind, n, cf, cd, A);
     for (int e = 0; e < 9; ++e) dst[e] = (float)A[e];
     dst[9] = dst[10] = dst[11] = 0.f;
 }
@@ -939,6 +1010,76 @@ __global__ void k_phi_x(const float4 *__restrict__ T, const uint8_t *__restrict_
     chunk_transfer(kind, L, cf, cd, PHI + t * 12);
 }
 
+// periodic rows, x kernel's cyclic scan: PER[row][kind][kPerXEntries][12], one
+// thread per (row, kind), FP64 products of FP64 chunk transfers (see rf3_internal.h)
+__device__ inline void m3_mul_d(const double *A, const double *B, double *C)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+__global__ void k_per_x(const float4 *__restrict__ T, const uint8_t *__restrict__ code, float *__restrict__ PER,
+                        int nx, int ny, int L)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)ny * 4) return;
+    const int row = (int)(t / 4), kind = (int)(t % 4);
+    const int clast = (nx - 1) / L, slast = (nx - 1) % L;
+    const float4 *tr = T + (long)row * nx;
+    const uint8_t *cr = code + (long)row * nx;
+    float *dst = PER + t * kPerXEntries * 12;
+    auto chunk = [&](int c, int n, double *A) {
+        auto cf = [&](int i) -> float4 {
+            const int x = c * L + i;
+            return x < nx ? tr[x] : make_float4(0.f, 0.f, 0.f, 0.f);
+        };
+        auto cd = [&](int i) -> uint8_t {
+            const int x = c * L + i;
+            return x < nx ? cr[x] : (uint8_t)(CODE_FRESET | CODE_BRESET);
+        };
+        chunk_transfer_d(kind, n, cf, cd, A);
+    };
+    auto put = [&](int e, const double *A) {
+        for (int q = 0; q < 9; ++q) dst[e * 12 + q] = A ? (float)A[q] : 0.f;
+        dst[e * 12 + 9] = dst[e * 12 + 10] = dst[e * 12 + 11] = 0.f;
+    };
+    for (int e = 0; e < kPerXEntries; ++e) put(e, nullptr);
+    const double I[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    double P[9], A[9], N[9], cyc[9];
+    for (int e = 0; e < 9; ++e) P[e] = I[e];
+    if (!(kind & 1)) {   // ascending: P_c = Phi_{c-1} .. Phi_0
+        for (int c = 0; c <= clast; ++c) {
+            put(c, P);
+            if (c < clast) {
+                chunk(c, L, A);
+                m3_mul_d(A, P, N);
+                for (int e = 0; e < 9; ++e) P[e] = N[e];
+            }
+        }
+        chunk(clast, slast + 1, A);
+        put(65, A);
+        m3_mul_d(A, P, cyc);
+    } else {             // descending: P_c = Phi_{c+1} .. Phi_{c_last - 1} Phi_last, P_{c_last} = I
+        put(clast, I);
+        chunk(clast, slast + 1, P);
+        for (int c = clast - 1; c >= 0; --c) {
+            put(c, P);
+            chunk(c, L, A);
+            m3_mul_d(A, P, N);
+            for (int e = 0; e < 9; ++e) P[e] = N[e];
+        }
+        for (int e = 0; e < 9; ++e) cyc[e] = P[e];
+    }
+    // W = (I - cyc)^-1 (adjugate)
+    double B[9];
+    for (int e = 0; e < 9; ++e) B[e] = I[e] - cyc[e];
+    const double c00 = B[4] * B[8] - B[5] * B[7], c01 = B[5] * B[6] - B[3] * B[8], c02 = B[3] * B[7] - B[4] * B[6];
+    const double det = B[0] * c00 + B[1] * c01 + B[2] * c02;
+    const double W[9] = {c00 / det, (B[2] * B[7] - B[1] * B[8]) / det, (B[1] * B[5] - B[2] * B[4]) / det,
+                         c01 / det, (B[0] * B[8] - B[2] * B[6]) / det, (B[2] * B[3] - B[0] * B[5]) / det,
+                         c02 / det, (B[1] * B[6] - B[0] * B[7]) / det, (B[0] * B[4] - B[1] * B[3]) / det};
+    put(64, W);
+}
+
 // ---------------------------------------------------------------- dispatch
 // compute units of the current device (cached per device)
 static int cu_count()
@@ -969,11 +1110,14 @@ int x_groups(int ny, int nplanes, int gmax)
 
 template <int L, bool ADJ>
 static hipError_t launch_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
-                           int nx, int ny, int nplanes, hipStream_t st)
+                           int nx, int ny, int nplanes, const float *PERT, hipStream_t st)
 {
     const int groups = x_groups(ny, nplanes, 8);
     const unsigned nb = (unsigned)(((ny + 7) / 8) * 8 * groups);
-    k_rf3x<L, ADJ><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups);
+    if (PERT)
+        k_rf3x<L, ADJ, true><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups, PERT);
+    else
+        k_rf3x<L, ADJ, false><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups, nullptr);
     return hipGetLastError();
 }
 
@@ -1012,15 +1156,15 @@ static hipError_t launch_y(const float *in, float *out, const float4 *T, const f
 
 #define RF_X_CASE(Lv)                                                                                     \
     case Lv:                                                                                              \
-        return adj ? launch_x<Lv, true>(in, out, T, LM, PHI, nx, ny, nplanes, st)                         \
-                   : launch_x<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, st);
+        return adj ? launch_x<Lv, true>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, st)                   \
+                   : launch_x<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, st);
 #define RF_Y_CASE(Lv)                                                                                     \
     case Lv:                                                                                              \
         return adj ? launch_y<Lv, true>(in, out, T, KY, LM, PHI, nx, ny, nplanes, st)                     \
                    : launch_y<Lv, false>(in, out, T, KY, LM, PHI, nx, ny, nplanes, st);
 
 hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int lx,
-                      int nx, int ny, int nplanes, bool adj, hipStream_t st)
+                      int nx, int ny, int nplanes, bool adj, const float *PERT, hipStream_t st)
 {
     switch (lx) {
         RF_X_CASE(1) RF_X_CASE(3) RF_X_CASE(5) RF_X_CASE(7) RF_X_CASE(9) RF_X_CASE(11) RF_X_CASE(13)
@@ -1090,6 +1234,13 @@ hipError_t setup_ky_y(const float4 *T, const uint8_t *code, float *KY, int nx, i
     const int nblk = (nx + kYCols - 1) / kYCols;
     const long n = (long)nblk * kYCols * kYWaves * 4;
     k_kvec_y<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(T, code, KY, nx, ny, ly, nblk);
+    return hipGetLastError();
+}
+
+hipError_t setup_per_x(const float4 *T, const uint8_t *code, float *PER, int nx, int ny, int lx, hipStream_t st)
+{
+    const long n = (long)ny * 4;
+    k_per_x<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(T, code, PER, nx, ny, lx);
     return hipGetLastError();
 }
 

@@ -16,6 +16,52 @@ __device__ inline long line_base(const LineGeom &G, long t, int &pl)
     return (long)ln * G.lstride;
 }
 
+// Where the two laps over a line start.  A line runs ascending from i0 and
+// descending from i1, n points each, wrapping around on a periodic row.  On
+// ordinary lines i0 = 0 and i1 = n-1.  A periodic row starts each lap at a
+// point where the state is reset (a segment start for the ascending lap, a
+// segment end for the descending one), so the lap needs no incoming state; a
+// periodic row with no land has no such point: W then points at its one-lap
+// fixed points (the state to start from is W times the state one lap from
+// zero leaves).
+struct Laps {
+    int i0, i1;
+    const double *W;
+};
+__device__ inline Laps laps(const LineGeom &G, long t, int pl, const uint8_t *code, long mb)
+{
+    Laps L{0, G.n - 1, nullptr};
+    if (!G.periodic) return L;
+    int a = -1, b = -1;
+    for (int i = 0; i < G.n && (a < 0 || b < 0); ++i) {
+        const uint8_t c = code[mb + (long)i * G.estride];
+        if (a < 0 && (c & CODE_FRESET)) a = i;
+        if (b < 0 && (c & CODE_BRESET)) b = i;
+    }
+    if (a >= 0) {
+        L.i0 = a;
+        L.i1 = b;
+    } else {
+        const int lev = G.coef_per_lev ? pl % G.nlev : 0;
+        L.W = G.per + ((long)lev * G.nlines + t % G.nlines) * kPerSeq;
+    }
+    return L;
+}
+__device__ inline int lap_index(int start, int step, int n, bool desc)
+{
+    int i = desc ? start - step : start + step;
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+// (a, b, c) <- W (a, b, c), W row-major 3x3
+template <class F>
+__device__ inline void apply_w(const double *W, F &a, F &b, F &c)
+{
+    const F x = a, y = b, z = c;
+    a = (F)(W[0] * x + W[1] * y + W[2] * z);
+    b = (F)(W[3] * x + W[4] * y + W[5] * z);
+    c = (F)(W[6] * x + W[7] * y + W[8] * z);
+}
+
 // ---------------------------------------------------------------- FP32
 // Third-order recurrence of eqs. "fort"/"bact" written on the state
 // (p_{i-1}, d1 = p_{i-1}-p_{i-2}, d2 = p_{i-2}-p_{i-3}):
@@ -36,8 +82,9 @@ __global__ void k_rf3_seq_f32(const float *in, float *out, const float4 *__restr
     const long fb = (long)pl * G.plane + lb;
     const long cb = plane_offset(G, pl, G.coef_per_lev) + lb;
     const long mb = plane_offset(G, pl, G.mask_per_lev) + lb;
+    const Laps lp = laps(G, t, pl, code, mb);
     float p1 = 0.f, d1 = 0.f, d2 = 0.f;
-    for (int i = 0; i < G.n; ++i) {
+    auto asc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_FRESET) { p1 = 0.f; d1 = 0.f; d2 = 0.f; }
@@ -47,10 +94,15 @@ __global__ void k_rf3_seq_f32(const float *in, float *out, const float4 *__restr
         const float tt = fmaf(-k.w, d2, fmaf(-k.z, d1, fmaf(-k.y, p1, g * s)));
         const float p = p1 + tt;
         d2 = d1; d1 = tt; p1 = p;
-        out[fb + e] = p;
+        if (store) out[fb + e] = p;
+    };
+    if (lp.W) {
+        for (int i = 0; i < G.n; ++i) asc(i, false);
+        apply_w(lp.W + kPerSeqDelta + 9 * (ADJ ? 2 : 0), p1, d1, d2);
     }
+    for (int s = 0; s < G.n; ++s) asc(lap_index(lp.i0, s, G.n, false), true);
     p1 = 0.f; d1 = 0.f; d2 = 0.f;
-    for (int i = G.n - 1; i >= 0; --i) {
+    auto desc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_BRESET) { p1 = 0.f; d1 = 0.f; d2 = 0.f; }
@@ -59,8 +111,13 @@ __global__ void k_rf3_seq_f32(const float *in, float *out, const float4 *__restr
         const float tt = fmaf(-k.w, d2, fmaf(-k.z, d1, fmaf(-k.y, p1, k.x * v)));
         const float p = p1 + tt;
         d2 = d1; d1 = tt; p1 = p;
-        out[fb + e] = (c & CODE_SEA) ? (ADJ ? k.x * p : p) : 0.f;
+        if (store) out[fb + e] = (c & CODE_SEA) ? (ADJ ? k.x * p : p) : 0.f;
+    };
+    if (lp.W) {
+        for (int i = G.n - 1; i >= 0; --i) desc(i, false);
+        apply_w(lp.W + kPerSeqDelta + 9 * (ADJ ? 3 : 1), p1, d1, d2);
     }
+    for (int s = 0; s < G.n; ++s) desc(lap_index(lp.i1, s, G.n, true), true);
 }
 
 // ---------------------------------------------------------------- FP64
@@ -76,8 +133,9 @@ __global__ void k_rf3_seq_f64(const double *in, double *out, const double4 *__re
     const long fb = (long)pl * G.plane + lb;
     const long cb = plane_offset(G, pl, G.coef_per_lev) + lb;
     const long mb = plane_offset(G, pl, G.mask_per_lev) + lb;
+    const Laps lp = laps(G, t, pl, code, mb);
     double p1 = 0, p2 = 0, p3 = 0;
-    for (int i = 0; i < G.n; ++i) {
+    auto asc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_FRESET) { p1 = 0; p2 = 0; p3 = 0; }
@@ -88,10 +146,15 @@ __global__ void k_rf3_seq_f64(const double *in, double *out, const double4 *__re
         v += k.z * p2;
         v += k.w * p3;
         p3 = p2; p2 = p1; p1 = v;
-        out[fb + e] = v;
+        if (store) out[fb + e] = v;
+    };
+    if (lp.W) {
+        for (int i = 0; i < G.n; ++i) asc(i, false);
+        apply_w(lp.W, p1, p2, p3);
     }
+    for (int s = 0; s < G.n; ++s) asc(lap_index(lp.i0, s, G.n, false), true);
     p1 = 0; p2 = 0; p3 = 0;
-    for (int i = G.n - 1; i >= 0; --i) {
+    auto desc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_BRESET) { p1 = 0; p2 = 0; p3 = 0; }
@@ -101,8 +164,13 @@ __global__ void k_rf3_seq_f64(const double *in, double *out, const double4 *__re
         v += k.z * p2;
         v += k.w * p3;
         p3 = p2; p2 = p1; p1 = v;
-        out[fb + e] = (c & CODE_SEA) ? v : 0.0;
+        if (store) out[fb + e] = (c & CODE_SEA) ? v : 0.0;
+    };
+    if (lp.W) {
+        for (int i = G.n - 1; i >= 0; --i) desc(i, false);
+        apply_w(lp.W + 9, p1, p2, p3);
     }
+    for (int s = 0; s < G.n; ++s) desc(lap_index(lp.i1, s, G.n, true), true);
 }
 
 // Transpose of k_rf3_seq_f64 (G^T = D_beta L^-T D_beta U^-T):
@@ -119,9 +187,12 @@ __global__ void k_rf3_seq_f64_adj(const double *in, double *out, const double4 *
     const long fb = (long)pl * G.plane + lb;
     const long cb = plane_offset(G, pl, G.coef_per_lev) + lb;
     const long mb = plane_offset(G, pl, G.mask_per_lev) + lb;
+    const Laps lp = laps(G, t, pl, code, mb);
+    const int n = G.n;
+    auto coef = [&](int i) { return C[cb + (long)(((i % n) + n) % n) * G.estride]; };
     double z1 = 0, z2 = 0, z3 = 0;
     double4 k1 = make_double4(0, 0, 0, 0), k2 = k1, k3 = k1;   // coefficients of j-1, j-2, j-3
-    for (int i = 0; i < G.n; ++i) {
+    auto asc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_FRESET) { z1 = 0; z2 = 0; z3 = 0; }
@@ -132,11 +203,17 @@ __global__ void k_rf3_seq_f64_adj(const double *in, double *out, const double4 *
         v += k3.w * z3;
         z3 = z2; z2 = z1; z1 = v;
         k3 = k2; k2 = k1; k1 = k;
-        out[fb + e] = k.x * v;
+        if (store) out[fb + e] = k.x * v;
+    };
+    if (lp.W) {   // a cycle: the points before j = 0 are n-1, n-2, n-3
+        k1 = coef(-1); k2 = coef(-2); k3 = coef(-3);
+        for (int i = 0; i < n; ++i) asc(i, false);
+        apply_w(lp.W + 18, z1, z2, z3);
     }
+    for (int s = 0; s < n; ++s) asc(lap_index(lp.i0, s, n, false), true);
     z1 = 0; z2 = 0; z3 = 0;
     k1 = make_double4(0, 0, 0, 0); k2 = k1; k3 = k1;              // coefficients of j+1, j+2, j+3
-    for (int i = G.n - 1; i >= 0; --i) {
+    auto desc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_BRESET) { z1 = 0; z2 = 0; z3 = 0; }
@@ -147,8 +224,14 @@ __global__ void k_rf3_seq_f64_adj(const double *in, double *out, const double4 *
         v += k3.w * z3;
         z3 = z2; z2 = z1; z1 = v;
         k3 = k2; k2 = k1; k1 = k;
-        out[fb + e] = (c & CODE_SEA) ? k.x * v : 0.0;
+        if (store) out[fb + e] = (c & CODE_SEA) ? k.x * v : 0.0;
+    };
+    if (lp.W) {   // the points after j = n-1 are 0, 1, 2
+        k1 = coef(n); k2 = coef(n + 1); k3 = coef(n + 2);
+        for (int i = n - 1; i >= 0; --i) desc(i, false);
+        apply_w(lp.W + 27, z1, z2, z3);
     }
+    for (int s = 0; s < n; ++s) desc(lap_index(lp.i1, s, n, true), true);
 }
 
 // ---------------------------------------------------------------- 1st-RF
@@ -167,8 +250,9 @@ __global__ void k_rf1_seq_f64(const double *in, double *out, const double2 *__re
     const long fb = (long)pl * G.plane + lb;
     const long cb = plane_offset(G, pl, G.coef_per_lev) + lb;
     const long mb = plane_offset(G, pl, G.mask_per_lev) + lb;
+    const Laps lp = laps(G, t, pl, code, mb);
     double p = 0;
-    for (int i = 0; i < G.n; ++i) {
+    auto asc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_FRESET) p = 0;
@@ -176,17 +260,27 @@ __global__ void k_rf1_seq_f64(const double *in, double *out, const double2 *__re
         double s = in[fb + e];
         if (FIRST && !(c & CODE_SEA)) s = 0.0;
         p = k.y * s + k.x * p;
-        out[fb + e] = p;
+        if (store) out[fb + e] = p;
+    };
+    if (lp.W) {
+        for (int i = 0; i < G.n; ++i) asc(i, false);
+        p *= lp.W[kPerSeqRf1];
     }
+    for (int s = 0; s < G.n; ++s) asc(lap_index(lp.i0, s, G.n, false), true);
     p = 0;
-    for (int i = G.n - 1; i >= 0; --i) {
+    auto desc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_BRESET) p = 0;
         const double2 k = C[cb + e];
         p = k.y * out[fb + e] + k.x * p;
-        out[fb + e] = (LAST && !(c & CODE_SEA)) ? 0.0 : p;
+        if (store) out[fb + e] = (LAST && !(c & CODE_SEA)) ? 0.0 : p;
+    };
+    if (lp.W) {
+        for (int i = G.n - 1; i >= 0; --i) desc(i, false);
+        p *= lp.W[kPerSeqRf1 + 1];
     }
+    for (int s = 0; s < G.n; ++s) desc(lap_index(lp.i1, s, G.n, true), true);
 }
 
 // ---------------------------------------------------------------- launchers

@@ -27,8 +27,9 @@ hipError_t seq_rf1_f64(const double *in, double *out, const double2 *C, const ui
 
 namespace rf {
 // tiled FP32 kernels (sweep_fast.hip); hipErrorNotSupported when the tile size is not covered
+// PERT: cyclic-scan tables of periodic rows (rf3_internal.h), or null
 hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int lx,
-                      int nx, int ny, int nplanes, bool adj, hipStream_t st);
+                      int nx, int ny, int nplanes, bool adj, const float *PERT, hipStream_t st);
 hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
                       const float *PHI, int ly, int nx, int ny, int nplanes, bool adj, hipStream_t st);
 // batched forms over a work list: x units of one launch share the occupancy
@@ -42,4 +43,5 @@ int x_groups(int ny, int nplanes, int gmax);
 hipError_t setup_phi_y(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int ly, hipStream_t st);
 hipError_t setup_ky_y(const float4 *T, const uint8_t *code, float *KY, int nx, int ny, int ly, hipStream_t st);
 hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int lx, hipStream_t st);
+hipError_t setup_per_x(const float4 *T, const uint8_t *code, float *PER, int nx, int ny, int lx, hipStream_t st);
 }  // namespace rf

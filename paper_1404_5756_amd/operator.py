@@ -20,10 +20,12 @@ class HorizontalCovariance:
     """Operator V_H (3rd-RF) with its adjoint and the 1st-RF baseline on one grid.
 
     mask: [mask_nlev][ny][nx] (nonzero = sea); sigma_x, sigma_y: [sigma_nlev][ny][nx] in grid units.
+    periodic_x: zonally periodic rows (RF_PERIODIC_X); exact_ends: exact end conditions of the
+    3rd-RF (RF_EXACT_ENDS).
     """
 
     def __init__(self, mask, sigma_x, sigma_y, nlev, n_img=0, qmode="literal", k1=5, device="cuda",
-                 stream=None):
+                 stream=None, periodic_x=False, exact_ends=False):
         mask = np.asarray(mask.cpu() if isinstance(mask, torch.Tensor) else mask)
         if mask.ndim == 2:
             mask = mask[None]
@@ -35,7 +37,8 @@ class HorizontalCovariance:
             sy = sy[None]
         ny, nx = mask.shape[1:]
         self.device = torch.device(device)
-        self.grid = rf3.make_grid(nx, ny, nlev, mask.shape[0], sx.shape[0], n_img, qmode, k1)
+        flags = (rf3.RF_PERIODIC_X if periodic_x else 0) | (rf3.RF_EXACT_ENDS if exact_ends else 0)
+        self.grid = rf3.make_grid(nx, ny, nlev, mask.shape[0], sx.shape[0], n_img, qmode, k1, flags)
         nbytes = rf3.rf_coeffs_bytes(self.grid)
         if nbytes == 0:
             raise rf3.RFError(rf3.RF_E_SHAPE, "rf_coeffs_bytes")

@@ -19,12 +19,13 @@ RF_OK, RF_E_ARG, RF_E_SHAPE, RF_E_SIGMA, RF_E_HIP, RF_E_UNSUPPORTED = 0, -1, -2,
 RF_FP32, RF_FP64 = 0, 1
 RF_Q_LITERAL, RF_Q_VARMATCH, RF_Q_FIT = 0, 1, 2
 RF_CG_RR, RF_CG_PQ, RF_CG_RR_NEW, RF_CG_SLOTS = 0, 1, 2, 8
+RF_PERIODIC_X, RF_EXACT_ENDS = 1, 2
 QMODES = {"literal": RF_Q_LITERAL, "varmatch": RF_Q_VARMATCH, "fit": RF_Q_FIT}
 
 
 class rf_grid(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("nx", "ny", "nlev", "mask_nlev", "sigma_nlev", "n_img", "qmode", "k1")]
+                ("nx", "ny", "nlev", "mask_nlev", "sigma_nlev", "n_img", "qmode", "k1", "flags")]
 
     def __repr__(self):
         return "rf_grid(" + ", ".join(f"{n}={getattr(self, n)}" for n, _ in self._fields_) + ")"
@@ -148,10 +149,10 @@ def _stream(stream):
     return stream.cuda_stream
 
 
-def make_grid(nx, ny, nlev, mask_nlev=1, sigma_nlev=1, n_img=0, qmode=RF_Q_LITERAL, k1=5) -> rf_grid:
+def make_grid(nx, ny, nlev, mask_nlev=1, sigma_nlev=1, n_img=0, qmode=RF_Q_LITERAL, k1=5, flags=0) -> rf_grid:
     if isinstance(qmode, str):
         qmode = QMODES[qmode]
-    return rf_grid(nx, ny, nlev, mask_nlev, sigma_nlev, n_img, qmode, k1)
+    return rf_grid(nx, ny, nlev, mask_nlev, sigma_nlev, n_img, qmode, k1, flags)
 
 
 def rf_coeffs_bytes(g: rf_grid) -> int:

@@ -60,7 +60,7 @@ def test_plan_header_and_unit_count():
     assert nb > 0 and nb % 256 == 0
     buf = rf3.rf3_batch_plan(items)
     magic, version, n_items, n_units, off_e, off_u, total = struct.unpack_from("<IIiiQQQ", buf, 0)
-    assert magic == 0x50424652 and version == 2
+    assert magic == 0x50424652 and version == 3
     assert n_items == len(items) and total == nb == len(buf)
     exp = _expected_units(items)
     lo = sum(exp.values())
@@ -68,9 +68,10 @@ def test_plan_header_and_unit_count():
     assert n_units >= lo and n_units % 8 == 0
     assert off_e == 64 and off_u % 256 == 0 and off_u + 16 * n_units <= total
     # entry 1 (1440 x 720 x 50): pointers and sizes as given
-    e = struct.unpack_from("<QQ7Qiiii", buf, off_e + 1 * 88)   # in, out, T[2], KY, LM[2], PHI[2], sizes
+    # in, out, T[2], KY, LM[2], PHI[2], PER, END[2], sizes
+    e = struct.unpack_from("<QQ10Qiiii", buf, off_e + 1 * 112)
     assert e[0] == items[1][2] and e[1] == items[1][3]
-    assert e[9:12] == (1440, 720, 50)
+    assert e[12:15] == (1440, 720, 50)
     # the 3-D-mask item runs the sequential path: no units reference it
     units = [struct.unpack_from("<iiii", buf, off_u + 16 * k) for k in range(n_units)]
     assert all(u[0] != 3 for u in units)

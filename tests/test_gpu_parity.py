@@ -140,8 +140,8 @@ def test_coefficient_tables_match_oracle(case, orc):
     w, x, P, _, _, op = case
     blk = _block(op)
     hdr = np.frombuffer(blk[:256].tobytes(), dtype=np.uint64)
-    # header: magic/version (8 B), grid (32 B), npts_c, npts_m, then 6 offset pairs
-    off = {name: hdr[7 + 2 * k: 9 + 2 * k] for k, name in enumerate(("f32", "a32", "d32", "f64", "r1", "code"))}
+    # header: magic/version (8 B), grid (36 B, padded to 40), npts_c, npts_m, then 6 offset pairs
+    off = {name: hdr[8 + 2 * k: 10 + 2 * k] for k, name in enumerate(("f32", "a32", "d32", "f64", "r1", "code"))}
     npts = w.nx * w.ny * w.sigma_x.shape[0]
     for d, sig in enumerate((w.sigma_x, w.sigma_y)):
         f64 = np.frombuffer(blk[off["f64"][d]: off["f64"][d] + 32 * npts].tobytes(), np.float64).reshape(-1, 4)
@@ -158,7 +158,7 @@ def test_coast_codes_match_oracle_segments(case, orc):
     w, x, P, _, _, op = case
     blk = _block(op)
     hdr = np.frombuffer(blk[:256].tobytes(), dtype=np.uint64)
-    code_off = hdr[17:19]
+    code_off = hdr[18:20]
     ml = w.mask.shape[0]
     for d in range(2):
         codes = blk[code_off[d]: code_off[d] + ml * w.nx * w.ny].reshape(ml, w.ny, w.nx)

@@ -25,9 +25,17 @@ LineGeom geom(const rf_grid *g, int dir, int nlev, int nfields, const void *coef
     G.coef_per_lev = g->sigma_nlev > 1;
     G.periodic = dir == 0 && (g->flags & RF_PERIODIC_X);
     G.per = nullptr;
-    if (G.periodic) {
+    G.endd = nullptr;
+    G.endf = nullptr;
+    G.end_per_lev = 0;
+    if (g->flags) {
         const BlockHeader h = layout(g);
-        G.per = reinterpret_cast<const double *>(reinterpret_cast<const char *>(coef) + h.off_perseq);
+        if (G.periodic) G.per = reinterpret_cast<const double *>(reinterpret_cast<const char *>(coef) + h.off_perseq);
+        if (h.end_nlev) {
+            G.endd = reinterpret_cast<const double *>(reinterpret_cast<const char *>(coef) + h.off_endd[dir]);
+            G.endf = reinterpret_cast<const float *>(reinterpret_cast<const char *>(coef) + h.off_endf[dir]);
+            G.end_per_lev = h.end_nlev > 1;
+        }
     }
     return G;
 }
@@ -82,14 +90,16 @@ static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void
     const int nplanes = nlev * nfields;
     if (tiled2d && dir == 0 && h.lx) {
         const float *pert = h.off_perx ? tab<float>(coef, h.off_perx) : nullptr;
+        const float *endt = h.off_endf[0] ? tab<float>(coef, h.off_endf[0]) : nullptr;
         hipError_t e = fast_rf3_x(in, out, tab<float4>(coef, h.off_f32[0]), tab<uint64_t>(coef, h.off_lmx),
-                                  tab<float>(coef, h.off_phix), h.lx, g->nx, g->ny, nplanes, adj, pert, st);
+                                  tab<float>(coef, h.off_phix), h.lx, g->nx, g->ny, nplanes, adj, pert, endt, st);
         if (e != hipErrorNotSupported) return e;
     }
     if (tiled2d && dir == 1 && h.ly) {
+        const float *endt = h.off_endf[1] ? tab<float>(coef, h.off_endf[1]) : nullptr;
         hipError_t e = fast_rf3_y(in, out, tab<float4>(coef, h.off_f32[1]), tab<float>(coef, h.off_ky),
                                   tab<uint64_t>(coef, h.off_lmy), tab<float>(coef, h.off_phiy), h.ly, g->nx, g->ny,
-                                  nplanes, adj, st);
+                                  nplanes, adj, endt, st);
         if (e != hipErrorNotSupported) return e;
     }
     const LineGeom G = geom(g, dir, nlev, nfields, coef);

@@ -203,7 +203,7 @@ __global__ void k_lanemask_x(const uint8_t *__restrict__ code, uint64_t *__restr
     const int i = (int)(t % lxp);
     const long lrow = t / lxp;               // level * ny + row
     const uint8_t *c = code + lrow * nx;
-    uint64_t f = ~0ull, b = ~0ull, s = 0;   // s collects SEA; the table stores its complement
+    uint64_t f = ~0ull, b = ~0ull, s = 0, en = 0;   // s collects SEA; the table stores its complement
     if (i < lx) {
         f = b = 0;
         for (int ch = 0; ch < 64; ++ch) {
@@ -212,12 +212,14 @@ __global__ void k_lanemask_x(const uint8_t *__restrict__ code, uint64_t *__restr
             f |= (uint64_t)((v & CODE_FRESET) != 0) << ch;
             b |= (uint64_t)((v & CODE_BRESET) != 0) << ch;
             s |= (uint64_t)((v & CODE_SEA) != 0) << ch;
+            en |= (uint64_t)((v & CODE_ACTIVE) && (v & CODE_BRESET)) << ch;
         }
     }
-    uint64_t *o = lm + lrow * 3 * lxp + i;
+    uint64_t *o = lm + lrow * kLaneMasks * lxp + i;
     o[0] = f;
     o[lxp] = b;
     o[2 * lxp] = ~s;
+    o[3 * lxp] = en;
 }
 
 // Lane masks of the y kernel: one thread per (mask level, column block, entry e
@@ -232,7 +234,7 @@ __global__ void k_lanemask_y(const uint8_t *__restrict__ code, uint64_t *__restr
     const int e = (int)(t % lys), r = e - 8;
     const long lb = t / lys;                  // level * nblk + blk
     const int blk = (int)(lb % nblk), lev = (int)(lb / nblk);
-    uint64_t f = 0, b = 0, s = 0;
+    uint64_t f = 0, b = 0, s = 0, en = 0;
     for (int j = 0; j < kYCols; ++j) {
         const int x = blk * kYCols + j;
         const uint8_t v = (x < nx && r >= 0 && r < ny) ? code[((long)lev * ny + r) * nx + x]
@@ -240,11 +242,13 @@ __global__ void k_lanemask_y(const uint8_t *__restrict__ code, uint64_t *__restr
         f |= (uint64_t)((v & CODE_FRESET) != 0) << j;
         b |= (uint64_t)((v & CODE_BRESET) != 0) << j;
         s |= (uint64_t)((v & CODE_SEA) != 0) << j;
+        en |= (uint64_t)((v & CODE_ACTIVE) && (v & CODE_BRESET)) << j;
     }
-    uint64_t *o = lm + lb * 3 * lys + e;
+    uint64_t *o = lm + lb * kLaneMasks * lys + e;
     o[0] = f;
     o[lys] = b;
     o[2 * lys] = ~s;
+    o[3 * lys] = en;
 }
 
 // ---- periodic rows: one-lap fixed points of the line-sequential kernels
@@ -315,6 +319,134 @@ __global__ void k_perseq(const char *__restrict__ blk, double *__restrict__ out,
     o[kPerSeqRf1 + 2] = o[kPerSeqRf1 + 3] = 0.0;
 }
 
+// ---- exact end conditions: the 3x3 end matrices at every segment end
+// Solve A x = b (n x n row-major, partial pivoting), b overwritten by x.
+__device__ inline void solve_dense(int n, double *A, double *b)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[r * n + c]) > fabs(A[piv * n + c])) piv = r;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) { const double t = A[c * n + k]; A[c * n + k] = A[piv * n + k]; A[piv * n + k] = t; }
+            const double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double v = b[r];
+        for (int k = r + 1; k < n; ++k) v -= A[r * n + k] * b[k];
+        b[r] = v / A[r * n + r];
+    }
+}
+
+// Past a segment end e the input is zero and e's coefficients continue, so the
+// causal state x_j = (p_j, p_{j-1}, p_{j-2}) follows x_j = C x_{j-1} with the
+// companion matrix C = ((a1, a2, a3), (1, 0, 0), (0, 1, 0)), and the anti-causal
+// values past e are (o_{e+1}, o_{e+2}, o_{e+3}) = M (p_e, p_{e-1}, p_{e-2}) with
+// M = beta X C, X = sum_m C^m e1 e1^T C^m, i.e. X = e1 e1^T + C X C (9x9 solve).
+// Those values enter the anti-causal steps of e, e-1, e-2 through
+// J = ((a1_e, a2_e, a3_e), (a2_{e-1}, a3_{e-1}, 0), (a3_{e-2}, 0, 0)): the
+// forward anti-causal input at e - t gains (J M x)_t, and the adjoint adds
+// (M^T J^T z)_t to the transposed pass's w = beta z at e - t.  Rows of points
+// e-1, e-2 outside the segment are zero.
+//
+// For large sigma M has large entries that cancel on smooth data, so the FP32
+// paths apply the maps to accurately computed states, not to three stored
+// values: the causal state in increment form (p_e, p_e - p_{e-1}, p_{e-1} -
+// p_{e-2}) = D x with D = ((1,0,0), (1,-1,0), (0,1,-1)) (forward: J M D^-1;
+// line-sequential adjoint, whose first pass carries z in the same form:
+// M^T J^T D^-1), and, in the tiled adjoint, the transposed pass's state at e,
+// which is the costate of the anti-causal start state in increment form, mu =
+// D^-T J^T z (M^T D^T).
+// One thread per (end level, y, x), both directions: FP64 J M and M^T J^T (on
+// the values themselves), FP32 [3][12]: J M D^-1, M^T D^T, M^T J^T D^-1.
+__global__ void k_end(const char *__restrict__ blk, char *__restrict__ wblk, BlockHeader h)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = h.g.nx, ny = h.g.ny;
+    const long plane = (long)nx * ny;
+    if (t >= (long)h.end_nlev * plane) return;
+    const int lev = (int)(t / plane);
+    const long r = t % plane;
+    const int y = (int)(r / nx), x = (int)(r % nx);
+    const long mb = (h.g.mask_nlev > 1 ? lev : 0) * plane, cb = (h.g.sigma_nlev > 1 ? lev : 0) * plane;
+    for (int d = 0; d < 2; ++d) {
+        double *od = reinterpret_cast<double *>(wblk + h.off_endd[d]) + t * 18;
+        float *of = reinterpret_cast<float *>(wblk + h.off_endf[d]) + t * 36;
+        for (int q = 0; q < 18; ++q) od[q] = 0.0;
+        for (int q = 0; q < 36; ++q) of[q] = 0.f;
+        const uint8_t *code = reinterpret_cast<const uint8_t *>(blk + h.off_code[d]) + mb;
+        const double4 *C4 = reinterpret_cast<const double4 *>(blk + h.off_f64[d]) + cb;
+        const uint8_t ce = code[r];
+        if (!(ce & CODE_ACTIVE) || !(ce & CODE_BRESET)) continue;
+        const bool per = d == 0 && (h.g.flags & RF_PERIODIC_X);
+        const int n = d == 0 ? nx : ny, i = d == 0 ? x : y;
+        auto pt = [&](int k) -> long {   // point k steps before e along the line
+            int j = i - k;
+            if (per) j = ((j % n) + n) % n;
+            return d == 0 ? (long)y * nx + j : (long)j * nx + x;
+        };
+        const bool in1 = !(ce & CODE_FRESET);
+        const bool in2 = in1 && !(code[pt(1)] & CODE_FRESET);
+        const double4 c0 = C4[r];
+        const double4 c1 = in1 ? C4[pt(1)] : make_double4(1, 0, 0, 0);
+        const double4 c2 = in2 ? C4[pt(2)] : make_double4(1, 0, 0, 0);
+        const double Cm[9] = {c0.y, c0.z, c0.w, 1, 0, 0, 0, 1, 0};
+        double A[81], X[9];
+        for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v) {
+                double *row = A + 9 * (3 * u + v);
+                for (int w = 0; w < 9; ++w) row[w] = w == 3 * u + v ? 1.0 : 0.0;
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) row[3 * k + l] -= Cm[3 * u + k] * Cm[3 * l + v];
+                X[3 * u + v] = (u == 0 && v == 0) ? 1.0 : 0.0;
+            }
+        solve_dense(9, A, X);
+        double M[9];
+        for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v)
+                M[3 * u + v] = c0.x * (X[3 * u] * Cm[v] + X[3 * u + 1] * Cm[3 + v] + X[3 * u + 2] * Cm[6 + v]);
+        const double J[9] = {c0.y, c0.z, c0.w, in1 ? c1.z : 0.0, in1 ? c1.w : 0.0, 0.0, in2 ? c2.w : 0.0, 0.0, 0.0};
+        const bool keep[3] = {true, in1, in2};
+        // JM and (JM)^T; D^-1 = ((1,0,0), (1,-1,0), (1,-1,-1)), D^T = ((1,1,0), (0,-1,1), (0,0,-1))
+        const double Di[9] = {1, 0, 0, 1, -1, 0, 1, -1, -1};
+        const double Dt[9] = {1, 1, 0, 0, -1, 1, 0, 0, -1};
+        double JM[9], JMt[9], Mt[9];
+        for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v) {
+                double f = 0.0;
+                for (int k = 0; k < 3; ++k) f += J[3 * u + k] * M[3 * k + v];
+                JM[3 * u + v] = f;
+                Mt[3 * v + u] = M[3 * u + v];
+            }
+        for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v) JMt[3 * u + v] = JM[3 * v + u];
+        auto mul = [](const double *P, const double *Q, double *R) {
+            for (int u = 0; u < 3; ++u)
+                for (int v = 0; v < 3; ++v) R[3 * u + v] = P[3 * u] * Q[v] + P[3 * u + 1] * Q[3 + v] + P[3 * u + 2] * Q[6 + v];
+        };
+        double F[9], Ta[9], Sa[9];
+        mul(JM, Di, F);    // forward, on the causal increment state
+        mul(Mt, Dt, Ta);   // tiled adjoint, on the transposed pass's state
+        mul(JMt, Di, Sa);  // sequential adjoint, on z in increment form
+        for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v) {
+                const bool k = keep[u];
+                const bool kk = keep[u] && keep[v];
+                od[3 * u + v] = kk ? JM[3 * u + v] : 0.0;
+                od[9 + 3 * u + v] = kk ? JMt[3 * u + v] : 0.0;
+                of[3 * u + v] = k ? (float)F[3 * u + v] : 0.f;
+                of[12 + 3 * u + v] = k ? (float)Ta[3 * u + v] : 0.f;
+                of[24 + 3 * u + v] = k ? (float)Sa[3 * u + v] : 0.f;
+            }
+    }
+}
+
 bool grid_ok(const rf_grid *g)
 {
     if (!g) return false;
@@ -349,9 +481,9 @@ BlockHeader layout(const rf_grid *g)
     h.lx = tile_lx(g->nx);
     h.ly = tile_ly(g->ny);
     h.off_lmx = off;
-    if (h.lx) off = align256(off + (size_t)g->mask_nlev * g->ny * lmx_stride(h.lx) * 3 * 8);
+    if (h.lx) off = align256(off + (size_t)g->mask_nlev * g->ny * lmx_stride(h.lx) * kLaneMasks * 8);
     h.off_lmy = off;
-    if (h.ly) off = align256(off + (size_t)g->mask_nlev * ((g->nx + kYCols - 1) / kYCols) * lmy_stride(h.ly) * 3 * 8);
+    if (h.ly) off = align256(off + (size_t)g->mask_nlev * ((g->nx + kYCols - 1) / kYCols) * lmy_stride(h.ly) * kLaneMasks * 8);
     h.off_phiy = off;
     if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1)
         off = align256(off + (size_t)((g->nx + kYCols - 1) / kYCols) * 4 * kYWaves * kYCols * 12 * 4);
@@ -373,10 +505,8 @@ BlockHeader layout(const rf_grid *g)
         for (int d = 0; d < 2; ++d) {
             h.off_endd[d] = off;
             off = align256(off + (size_t)h.end_nlev * plane * 2 * 9 * 8);
-            if (tiled2d && (d == 0 ? h.lx : h.ly)) {
-                h.off_endf[d] = off;
-                off = align256(off + plane * 2 * 12 * 4);
-            }
+            h.off_endf[d] = off;
+            off = align256(off + (size_t)h.end_nlev * plane * 3 * 12 * 4);
         }
     }
     h.total_bytes = off;
@@ -442,6 +572,11 @@ extern "C" int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *si
         if (setup_per_x((const float4 *)(blk + h.off_f32[0]), (const uint8_t *)(blk + h.off_code[0]),
                         (float *)(blk + h.off_perx), g->nx, g->ny, h.lx, st) != hipSuccess)
             return RF_E_HIP;
+    }
+    if (h.end_nlev) {
+        const long n = (long)h.end_nlev * g->nx * g->ny;
+        k_end<<<(unsigned)((n + 63) / 64), 64, 0, st>>>(blk, blk, h);
+        if (hipGetLastError() != hipSuccess) return RF_E_HIP;
     }
     if (h.off_perseq) {
         const long n = (long)g->sigma_nlev * g->ny;

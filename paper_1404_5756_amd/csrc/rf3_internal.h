@@ -23,6 +23,9 @@ enum : uint8_t {
     CODE_ACTIVE = 8,   // sea or imaginary point (inside a segment)
 };
 
+// lane-mask slabs of the tiled kernels: FRESET, BRESET, not-SEA, segment end (ACTIVE and BRESET)
+constexpr int kLaneMasks = 4;
+
 // Tables per direction (0 = x, 1 = y).  Element index of every per-point table
 // is (level * ny + y) * nx + x, where level is the sigma level for coefficient
 // tables and the mask level for code tables.
@@ -48,8 +51,8 @@ struct BlockHeader {
     int32_t pad[3];
     // lane-mask tables of the tiled FP32 kernels (0 when the shape is not tiled)
     int32_t lx, ly;           // points per lane along x (64 lanes per row), per wave along y (16 waves)
-    uint64_t off_lmx;         // uint64 [mask_nlev][ny][3][lxp]: FRESET, BRESET, not-SEA lane masks, bit c = chunk c
-    uint64_t off_lmy;         // uint64 [mask_nlev][nblk][3][lys]: bit j = column 64*blk + j, entry 8+r = row r
+    uint64_t off_lmx;         // uint64 [mask_nlev][ny][kLaneMasks][lxp]: FRESET, BRESET, not-SEA, end; bit c = chunk c
+    uint64_t off_lmy;         // uint64 [mask_nlev][nblk][kLaneMasks][lys]: bit j = column 64*blk + j, entry 8+r = row r
     uint64_t off_phiy;        // float [nblk][4][16][64][12]: y-chunk transfer matrices (2-D mask and sigma only)
     uint64_t off_phix;        // float [ny][4][64][12]: x-chunk transfer matrices (2-D mask and sigma only)
     uint64_t off_ky;          // float [4][ny][nx][3]: y local-pass K vectors (2-D mask and sigma only)
@@ -58,7 +61,9 @@ struct BlockHeader {
     uint64_t off_perseq;      // double [sigma_nlev][ny][kPerSeq]: one-lap fixed points of the sequential kernels
     // RF_EXACT_ENDS (0 otherwise): 3x3 end matrices at segment ends, zero elsewhere
     uint64_t off_endd[2];     // double [end_nlev][ny][nx][2][9]: forward J M, adjoint M^T J^T (on p and z)
-    uint64_t off_endf[2];     // float [ny][nx][2][12]: the same times diag(1/beta) (tiled kernels, 2-D only)
+    uint64_t off_endf[2];     // float [end_nlev][ny][nx][3][12]: the FP32 paths' maps on increment-form
+                              // states: forward J M D^-1, tiled adjoint M^T D^T, sequential adjoint
+                              // M^T J^T D^-1 (a row-major 3x3 in the first 9 floats of each 12)
     int32_t end_nlev;         // max(mask_nlev, sigma_nlev) when RF_EXACT_ENDS
     int32_t pad2;
 };
@@ -124,7 +129,7 @@ struct BatchEntry {
     const uint64_t *LM[2];
     const float *PHI[2];
     const float *PER;         // cyclic x scan tables (periodic rows), or null
-    const float *END[2];      // exact-end tables of the tiled kernels, or null
+    const float *END[2];      // exact-end maps of the tiled kernels, or null (unused: such items run per item)
     int32_t nx, ny, nplanes, pad;
 };
 struct BatchUnit {
@@ -144,6 +149,9 @@ struct LineGeom {
     int coef_per_lev; // same for coefficient tables
     int periodic;     // lines are cycles (periodic rows)
     const double *per;// periodic: one-lap fixed points [coefficient level][line][kPerSeq]
+    const double *endd;  // exact ends: [end level][ny][nx][2][9] end matrices, or null
+    const float *endf;   // exact ends: [end level][ny][nx][3][12] FP32 maps, or null
+    int end_per_lev;     // the end tables have one plane per level
 };
 
 __host__ __device__ inline long plane_offset(const LineGeom &G, int pl, int per_lev)

@@ -196,6 +196,51 @@ struct XRow {
             if (PER && i == s_hook) *save = x;
         }
     }
+    // asc<2> with exact ends: at a segment end (fourth mask slab) the state after
+    // the step (forward: the causal state (p, d1, d2); adjoint: before the reset,
+    // the costate of the anti-causal start state) times the point's 3x3 map N
+    // (EN: this row's maps, 36 floats per point, this kernel's at offset 0)
+    // is added to v at the point and the two before it; corrections for points
+    // of the previous chunk accumulate in co1 (its last point) and co2 (the one
+    // before).
+    __device__ __forceinline__ void asc2_end(St &x, float *v, const float *EN, int lane, float &co1, float &co2) const
+    {
+        const int z = fresh_int(0);
+        mask_ptr rp = lm + (ADJ ? LP : 0) + z;
+        mask_ptr ep = lm + 3 * LP + z;
+        const int x0 = lane * L;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const uint64_t m = rp[i];
+            const uint64_t em = ep[i];
+            St s;
+            if (!ADJ) {
+                st_reset(x, m);
+                fwd_step(x, v[i], kg[i], k2[i], k3[i]);
+                v[i] = kb[i] * x.a;
+                s = x;
+            } else {
+                v[i] = adj_step<true>(x, v[i], kb[i], kg[i], k2[i], k3[i]);
+                s = x;
+                st_reset(x, m);
+            }
+            if (em != 0 && ((em >> lane) & 1)) {
+                const float *N = EN + (long)(x0 + i) * 36;
+                float n[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) n[q] = N[q];
+                const float r0 = fmaf(n[0], s.a, fmaf(n[1], s.b, n[2] * s.c));
+                const float r1 = fmaf(n[3], s.a, fmaf(n[4], s.b, n[5] * s.c));
+                const float r2 = fmaf(n[6], s.a, fmaf(n[7], s.b, n[8] * s.c));
+                v[i] += r0;
+                if (i >= 1) v[i >= 1 ? i - 1 : 0] += r1;
+                else co1 += r1;
+                if (i >= 2) v[i >= 2 ? i - 2 : 0] += r2;
+                else if (i == 1) co1 += r2;
+                else co2 += r2;
+            }
+        }
+    }
     // descending sweep over my chunk; MODE 2 also applies the sea mask to the output
     template <int MODE, bool PER = false>
     __device__ __forceinline__ void desc(St &x, float *v, int s_hook = 0, bool inj_lane = false,
@@ -357,10 +402,11 @@ constexpr int x_stage_floats() { return 256 * ((L + 3) / 4); }   // whole dwordx
 
 // Lines of one row: planes grp, grp + groups, ... (4 waves, interleaved).
 // K: [2][64 * kKs] scan matrices, stage: this wave's LDS staging area.
-template <int L, bool ADJ, bool PER = false>
+template <int L, bool ADJ, bool PER = false, bool END = false>
 __device__ __forceinline__ void x_rows(const float *in, float *out, const float4 *T, const uint64_t *LM,
                                        const float *PHI, int nx, int ny, int nplanes, int row, int grp,
-                                       int groups, float *K, float *stg, const float *PERT = nullptr)
+                                       int groups, float *K, float *stg, const float *PERT = nullptr,
+                                       const float *ENDT = nullptr)
 {
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long plane = (long)nx * ny;
@@ -379,7 +425,7 @@ __device__ __forceinline__ void x_rows(const float *in, float *out, const float4
             R.k3[i] = __uint_as_float(c.w);
         }
     }
-    R.lm = as_const(LM + (long)row * 3 * XRow<L, ADJ>::LP);
+    R.lm = as_const(LM + (long)row * kLaneMasks * XRow<L, ADJ>::LP);
     if (wave < 2) {   // wave 0: ascending scan matrices, wave 1: descending
         const float *p = PHI + (((long)row * 4 + (ADJ ? 2 : 0) + wave) * 64 + lane) * 12;
         float A[9];
@@ -426,7 +472,19 @@ __device__ __forceinline__ void x_rows(const float *in, float *out, const float4
         if (!PER) {
             R.template asc<1>(x, v);
             x = ks_carry<false>(x, K, lane);
-            R.template asc<2>(x, v);
+            if (!END) {
+                R.template asc<2>(x, v);
+            } else {
+                // exact ends: at a segment end the pass adds N (its state) to the
+                // anti-causal inputs of the point and the two before it; those of the
+                // previous chunk go back to it (wave shifts)
+                float co1 = 0.f, co2 = 0.f;
+                R.asc2_end(x, v, ENDT + (long)row * nx * 36 + (ADJ ? 12 : 0), lane, co1, co2);
+                const float b1 = dpp<DPP_WAVE_SHL1, 0xF>(co1), b2 = dpp<DPP_WAVE_SHL1, 0xF>(co2);
+                v[L - 1] += b1;
+                if (L >= 2) v[L >= 2 ? L - 2 : 0] += b2;
+                else v[L - 1] += dpp<DPP_WAVE_SHL1, 0xF>(b2);
+            }
             St y{0.f, 0.f, 0.f};
             R.template desc<1>(y, v);
             y = ks_carry<true>(y, K + 64 * kKs, lane);
@@ -495,10 +553,11 @@ __device__ __forceinline__ void x_rows(const float *in, float *out, const float4
     }
 }
 
-template <int L, bool ADJ, bool PER>
+template <int L, bool ADJ, bool PER, bool END>
 __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
     const float *in, float *out, const float4 *__restrict__ T, const uint64_t *__restrict__ LM,
-    const float *__restrict__ PHI, int nx, int ny, int nplanes, int groups, const float *__restrict__ PERT)
+    const float *__restrict__ PHI, int nx, int ny, int nplanes, int groups, const float *__restrict__ PERT,
+    const float *__restrict__ ENDT)
 {
     __shared__ float K[2 * 64 * kKs];
     __shared__ __align__(16) float stage[kXWaves][x_stage_floats<L>()];
@@ -507,8 +566,8 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
     const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
     const int row = (slot / groups) * 8 + xcd, grp = slot % groups;
     if (row >= ny) return;
-    x_rows<L, ADJ, PER>(in, out, T, LM, PHI, nx, ny, nplanes, row, grp, groups, K,
-                        stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)], PERT);
+    x_rows<L, ADJ, PER, END>(in, out, T, LM, PHI, nx, ny, nplanes, row, grp, groups, K,
+                             stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)], PERT, ENDT);
 }
 
 // Batched form: one workgroup per work unit {item, row, group, groups}; the
@@ -567,10 +626,11 @@ constexpr int kYWin = 2;
 // of each plane.  phi: [2][16][64 * 9] in LDS (filled by y_planes); bsh: LDS
 // array of [2][16][2][64 * 3] floats, used here as [2][16][P][64 * 3].
 // KY: the local passes' K vectors [4 kinds][ny][nx][3].
-template <int L, bool ADJ, int P>
+template <int L, bool ADJ, int P, bool END = false>
 __device__ __forceinline__ void y_unit(const float *in, float *out, const float4 *T, const float *KY,
                                        const uint64_t *LM, int nx_, int ny_, int blk, int pl0,
-                                       float (*phi)[kYWaves][kYCols * 9], float *bsh_raw)
+                                       float (*phi)[kYWaves][kYCols * 9], float *bsh_raw,
+                                       const float *ENDT = nullptr, float *xch = nullptr)
 {
     auto bsh = reinterpret_cast<float (*)[kYWaves][P][kYCols * 3]>(bsh_raw);
     constexpr int LB = (L + 7) / 8;   // 8-row mask blocks per chunk
@@ -578,7 +638,7 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
     const int col = blk * kYCols + lane;
     const long plane = (long)nx_ * ny_;
     const int lys = lmy_stride(L);
-    const uint64_t *lm = LM + (long)blk * 3 * lys + 8;   // entry r = row r
+    const uint64_t *lm = LM + (long)blk * kLaneMasks * lys + 8;   // entry r = row r
     // byte offset of my column in the field; columns past the grid get 2^29, past
     // every table (the y kernels need nx * ny < 2^27), so loads read 0 and stores
     // are dropped.  The coefficient (16 B) and K (12 B) offsets are 4x and 3x this,
@@ -595,6 +655,10 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
         // enclosing loop's preheader (hoisted, they would be live in SGPRs across it)
         const int r0 = fresh_int(w * L), ny = fresh_int(ny_), rowb = fresh_int(nx_ * 4), nx = fresh_int(nx_);
         float v[P][L];
+        float co1[P], co2[P];   // exact ends: corrections of the two rows above my chunk
+#pragma unroll
+        for (int p = 0; p < P; ++p) co1[p] = co2[p] = 0.f;
+        const uint64_t *ep_end = lm + 3 * lys + r0;
         Rsrc ri[P], ro[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -700,19 +764,43 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
                     const float bt = __uint_as_float(c.x), gm = __uint_as_float(c.y);
                     const float c2 = __uint_as_float(c.z), c3 = __uint_as_float(c.w);
                     const uint64_t mm = m64_of(m, q);
+                    // exact ends (ascending pass): lanes at a segment end load the row's map
+                    const uint64_t em = (END && !desc) ? ep_end[i] : 0;
+                    float n[9];
+                    const bool at_end = em != 0 && ((em >> lane) & 1);
+                    if (at_end) {
+                        const float *N = ENDT + ((long)(r0 + i) * nx + col) * 36 + (ADJ ? 12 : 0);
+#pragma unroll
+                        for (int e = 0; e < 9; ++e) n[e] = N[e];
+                    }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         float o;
+                        St sn;
                         if (!ADJ) {   // causal input beta_i s_i; the anti-causal one is prescaled
                             st_reset(x[p], mm);
                             fwd_step(x[p], desc ? v[p][i] : bt * v[p][i], gm, c2, c3);
                             o = x[p].a;
+                            sn = x[p];
                         } else {
                             o = adj_step<mode == 2>(x[p], v[p][i], bt, gm, c2, c3);
+                            sn = x[p];
                             st_reset(x[p], mm);
                         }
                         // forward ascending output: beta_i u_i, the anti-causal input
                         if (mode == 2) v[p][i] = desc ? zero_if(o, m64_of(sm, q)) : (ADJ ? o : bt * o);
+                        if (END && !desc && at_end) {
+                            // the anti-causal inputs of this row and the two above gain N (state)
+                            const float r0 = fmaf(n[0], sn.a, fmaf(n[1], sn.b, n[2] * sn.c));
+                            const float r1 = fmaf(n[3], sn.a, fmaf(n[4], sn.b, n[5] * sn.c));
+                            const float r2 = fmaf(n[6], sn.a, fmaf(n[7], sn.b, n[8] * sn.c));
+                            v[p][i] += r0;
+                            if (i >= 1) v[p][i >= 1 ? i - 1 : 0] += r1;
+                            else co1[p] += r1;
+                            if (i >= 2) v[p][i >= 2 ? i - 2 : 0] += r2;
+                            else if (i == 1) co1[p] += r2;
+                            else co2[p] += r2;
+                        }
                     }
                     if (last) {
                         if (soff < lim) {   // rows past the grid are not stored
@@ -764,6 +852,24 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
             pass(x, DC, std::integral_constant<int, 2>{});
         };
         sweep(std::false_type{});
+        if (END) {
+            // corrections of the rows above my chunk go to the waves that hold them
+            float(*corr)[P][2][kYCols] = reinterpret_cast<float(*)[P][2][kYCols]>(xch);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                corr[w][p][0][lane] = co1[p];   // row r0 - 1
+                corr[w][p][1][lane] = co2[p];   // row r0 - 2
+            }
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (w + 1 < kYWaves) {
+                    v[p][L - 1] += corr[w + 1][p][0][lane];
+                    if (L >= 2) v[p][L >= 2 ? L - 2 : 0] += corr[w + 1][p][1][lane];
+                }
+                if (L == 1 && w + 2 < kYWaves) v[p][L - 1] += corr[w + 2][p][1][lane];
+            }
+        }
         sweep(std::true_type{});
     }
 }
@@ -772,10 +878,11 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
 // and a one-plane unit for an odd count, run after single_after two-plane
 // units (varied across workgroups, so that they do not all reach their memory
 // phases together).
-template <int L, bool ADJ>
+template <int L, bool ADJ, bool END = false>
 __device__ __forceinline__ void y_planes(const float *in, float *out, const float4 *T, const float *KY,
                                          const uint64_t *LM, const float *PHI, int nx, int ny, int blk, int pa, int pb,
-                                         int single_after, float (*phi)[kYWaves][kYCols * 9], float *bsh)
+                                         int single_after, float (*phi)[kYWaves][kYCols * 9], float *bsh,
+                                         const float *ENDT = nullptr, float *xch = nullptr)
 {
     constexpr int PM = y_planes_per_lane(L);
     {
@@ -792,10 +899,10 @@ __device__ __forceinline__ void y_planes(const float *in, float *out, const floa
         // an odd count leaves one one-plane unit: it runs after single_after pairs
         const bool single = PM == 1 || pb - pa == 1 || (((pb - pa) & 1) && k >= single_after);
         if (single) {
-            y_unit<L, ADJ, 1>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
+            y_unit<L, ADJ, 1, END>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh, ENDT, xch);
             pa += 1;
         } else {
-            y_unit<L, ADJ, PM>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh);
+            y_unit<L, ADJ, PM, END>(in, out, T, KY, LM, nx, ny, blk, pa, phi, bsh, ENDT, xch);
             pa += PM;
         }
         __syncthreads();   // bsh is rewritten by the next unit
@@ -804,20 +911,22 @@ __device__ __forceinline__ void y_planes(const float *in, float *out, const floa
 
 // Workgroup (column block, slot): slot j of S takes planes [j n / S, (j+1) n / S),
 // its one-plane unit (odd counts) after (j + 2) % 3 two-plane units.
-template <int L, bool ADJ>
+template <int L, bool ADJ, bool END>
 __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float *out, const float4 *T,
                                                          const float *KY, const uint64_t *__restrict__ LM,
                                                          const float *__restrict__ PHI, int nx, int ny,
-                                                         int nplanes, int nblk, int nslot)
+                                                         int nplanes, int nblk, int nslot,
+                                                         const float *__restrict__ ENDT)
 {
     __shared__ float phi[2][kYWaves][kYCols * 9];
     __shared__ float bsh[2 * kYWaves * 2 * kYCols * 3];
+    __shared__ float xch[END ? kYWaves * 2 * 2 * kYCols : 1];   // exact ends: corrections between waves
     // XCD-aware order: all slots of a column block run on one XCD (shared L2)
     const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
     const int blk = (slot / nslot) * 8 + xcd, j = slot % nslot;
     if (blk >= nblk) return;
     const int pa = (int)((long)j * nplanes / nslot), pb = (int)((long)(j + 1) * nplanes / nslot);
-    y_planes<L, ADJ>(in, out, T, KY, LM, PHI, nx, ny, blk, pa, pb, (j + 2) % 3, phi, bsh);
+    y_planes<L, ADJ, END>(in, out, T, KY, LM, PHI, nx, ny, blk, pa, pb, (j + 2) % 3, phi, bsh, ENDT, xch);
 }
 
 // Batched form: one workgroup per work unit {item, column block, first and end
@@ -1110,14 +1219,20 @@ int x_groups(int ny, int nplanes, int gmax)
 
 template <int L, bool ADJ>
 static hipError_t launch_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
-                           int nx, int ny, int nplanes, const float *PERT, hipStream_t st)
+                           int nx, int ny, int nplanes, const float *PERT, const float *ENDT, hipStream_t st)
 {
     const int groups = x_groups(ny, nplanes, 8);
     const unsigned nb = (unsigned)(((ny + 7) / 8) * 8 * groups);
+    if (PERT && ENDT) return hipErrorNotSupported;   // periodic rows with exact ends: sequential kernels
     if (PERT)
-        k_rf3x<L, ADJ, true><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups, PERT);
+        k_rf3x<L, ADJ, true, false><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups, PERT,
+                                                                 nullptr);
+    else if (ENDT)
+        k_rf3x<L, ADJ, false, true><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups,
+                                                                 nullptr, ENDT);
     else
-        k_rf3x<L, ADJ, false><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups, nullptr);
+        k_rf3x<L, ADJ, false, false><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes, groups,
+                                                                  nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -1134,7 +1249,7 @@ static double y_range_cost(int n, int pm)
 
 template <int L, bool ADJ>
 static hipError_t launch_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
-                           const float *PHI, int nx, int ny, int nplanes, hipStream_t st)
+                           const float *PHI, int nx, int ny, int nplanes, const float *ENDT, hipStream_t st)
 {
     constexpr int PM = y_planes_per_lane(L);
     static_assert(PM == 1 || PM == 2, "planes per lane");
@@ -1150,21 +1265,25 @@ static hipError_t launch_y(const float *in, float *out, const float4 *T, const f
         if (best_cost < 0 || cost < best_cost - 1e-9) { best_cost = cost; best = sl; }
     }
     const unsigned nb = (unsigned)(nb8 * best);
-    k_rf3y<L, ADJ><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nplanes, nblk, best);
+    if (ENDT)
+        k_rf3y<L, ADJ, true><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nplanes, nblk, best, ENDT);
+    else
+        k_rf3y<L, ADJ, false><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nplanes, nblk, best,
+                                                          nullptr);
     return hipGetLastError();
 }
 
 #define RF_X_CASE(Lv)                                                                                     \
     case Lv:                                                                                              \
-        return adj ? launch_x<Lv, true>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, st)                   \
-                   : launch_x<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, st);
+        return adj ? launch_x<Lv, true>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, ENDT, st)             \
+                   : launch_x<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, ENDT, st);
 #define RF_Y_CASE(Lv)                                                                                     \
     case Lv:                                                                                              \
-        return adj ? launch_y<Lv, true>(in, out, T, KY, LM, PHI, nx, ny, nplanes, st)                     \
-                   : launch_y<Lv, false>(in, out, T, KY, LM, PHI, nx, ny, nplanes, st);
+        return adj ? launch_y<Lv, true>(in, out, T, KY, LM, PHI, nx, ny, nplanes, ENDT, st)               \
+                   : launch_y<Lv, false>(in, out, T, KY, LM, PHI, nx, ny, nplanes, ENDT, st);
 
 hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int lx,
-                      int nx, int ny, int nplanes, bool adj, const float *PERT, hipStream_t st)
+                      int nx, int ny, int nplanes, bool adj, const float *PERT, const float *ENDT, hipStream_t st)
 {
     switch (lx) {
         RF_X_CASE(1) RF_X_CASE(3) RF_X_CASE(5) RF_X_CASE(7) RF_X_CASE(9) RF_X_CASE(11) RF_X_CASE(13)
@@ -1175,7 +1294,8 @@ hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64
 }
 
 hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
-                      const float *PHI, int ly, int nx, int ny, int nplanes, bool adj, hipStream_t st)
+                      const float *PHI, int ly, int nx, int ny, int nplanes, bool adj, const float *ENDT,
+                      hipStream_t st)
 {
     // scalar row offsets into the coefficient table are 32-bit
     if ((long)nx * ny * 16 >= (1L << 31)) return hipErrorNotSupported;

@@ -52,6 +52,38 @@ __device__ inline int lap_index(int start, int step, int n, bool desc)
     int i = desc ? start - step : start + step;
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }
+// Exact ends, FP64 (G.endd): the anti-causal input at a segment end e and at
+// e-1, e-2 gains N (v_e, v_{e-1}, v_{e-2}), N the point's 3x3 end matrix
+// (forward: J M on the causal values p; adjoint: M^T J^T on the transposed
+// pass's z), v the values the causal lap left in `out`.  The corrections of e-1
+// and e-2 wait in pend1/pend2 for the next two descending steps.  (The FP32
+// kernel applies the same corrections in its ascending lap, from the state in
+// increment form, which large sigma needs: M's entries cancel on smooth data.)
+struct EndCorr {
+    double pend1 = 0.0, pend2 = 0.0;
+    template <class F>
+    __device__ inline double step(const LineGeom &G, long eb, int i, uint8_t c, const F *vals, long fb,
+                                  bool adj)
+    {
+        double add = pend1;
+        pend1 = pend2;
+        pend2 = 0.0;
+        if ((c & CODE_ACTIVE) && (c & CODE_BRESET)) {
+            const double *N = G.endd + (eb + (long)i * G.estride) * 18 + (adj ? 9 : 0);
+            double x[3];
+            for (int k = 0; k < 3; ++k) {
+                int j = i - k;
+                if (G.periodic) j = j < 0 ? j + G.n : j;
+                x[k] = j >= 0 ? (double)vals[fb + (long)j * G.estride] : 0.0;
+            }
+            add += N[0] * x[0] + N[1] * x[1] + N[2] * x[2];
+            pend1 += N[3] * x[0] + N[4] * x[1] + N[5] * x[2];
+            pend2 += N[6] * x[0] + N[7] * x[1] + N[8] * x[2];
+        }
+        return add;
+    }
+};
+
 // (a, b, c) <- W (a, b, c), W row-major 3x3
 template <class F>
 __device__ inline void apply_w(const double *W, F &a, F &b, F &c)
@@ -83,6 +115,7 @@ __global__ void k_rf3_seq_f32(const float *in, float *out, const float4 *__restr
     const long cb = plane_offset(G, pl, G.coef_per_lev) + lb;
     const long mb = plane_offset(G, pl, G.mask_per_lev) + lb;
     const Laps lp = laps(G, t, pl, code, mb);
+    const long eb = plane_offset(G, pl, G.end_per_lev) + lb;
     float p1 = 0.f, d1 = 0.f, d2 = 0.f;
     auto asc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
@@ -94,7 +127,24 @@ __global__ void k_rf3_seq_f32(const float *in, float *out, const float4 *__restr
         const float tt = fmaf(-k.w, d2, fmaf(-k.z, d1, fmaf(-k.y, p1, g * s)));
         const float p = p1 + tt;
         d2 = d1; d1 = tt; p1 = p;
-        if (store) out[fb + e] = p;
+        if (!store) return;
+        out[fb + e] = p;
+        if (G.endf && (c & CODE_ACTIVE) && (c & CODE_BRESET)) {
+            // exact end: the anti-causal input beta v at e - q gains N (p, d1, d2), the
+            // state in increment form; stored as v += N(...) / beta
+            const float *N = G.endf + (eb + e) * 36 + (ADJ ? 24 : 0);
+            for (int q = 0; q < 3; ++q) {
+                const float cq = fmaf(N[3 * q], p1, fmaf(N[3 * q + 1], d1, N[3 * q + 2] * d2));
+                if (cq == 0.f) continue;
+                int j = i - q;
+                if (j < 0) {
+                    if (!G.periodic) continue;
+                    j += G.n;
+                }
+                const long ej = (long)j * G.estride;
+                out[fb + ej] += cq / T1[cb + ej].x;
+            }
+        }
     };
     if (lp.W) {
         for (int i = 0; i < G.n; ++i) asc(i, false);
@@ -154,12 +204,15 @@ __global__ void k_rf3_seq_f64(const double *in, double *out, const double4 *__re
     }
     for (int s = 0; s < G.n; ++s) asc(lap_index(lp.i0, s, G.n, false), true);
     p1 = 0; p2 = 0; p3 = 0;
+    EndCorr ec;
+    const long eb = plane_offset(G, pl, G.end_per_lev) + lb;
     auto desc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_BRESET) { p1 = 0; p2 = 0; p3 = 0; }
         const double4 k = C[cb + e];
         double v = k.x * out[fb + e];
+        if (G.endd) v += ec.step(G, eb, i, c, out, fb, false);
         v += k.y * p1;
         v += k.z * p2;
         v += k.w * p3;
@@ -203,7 +256,7 @@ __global__ void k_rf3_seq_f64_adj(const double *in, double *out, const double4 *
         v += k3.w * z3;
         z3 = z2; z2 = z1; z1 = v;
         k3 = k2; k2 = k1; k1 = k;
-        if (store) out[fb + e] = k.x * v;
+        if (store) out[fb + e] = v;   // z; the descending lap takes beta z
     };
     if (lp.W) {   // a cycle: the points before j = 0 are n-1, n-2, n-3
         k1 = coef(-1); k2 = coef(-2); k3 = coef(-3);
@@ -213,12 +266,15 @@ __global__ void k_rf3_seq_f64_adj(const double *in, double *out, const double4 *
     for (int s = 0; s < n; ++s) asc(lap_index(lp.i0, s, n, false), true);
     z1 = 0; z2 = 0; z3 = 0;
     k1 = make_double4(0, 0, 0, 0); k2 = k1; k3 = k1;              // coefficients of j+1, j+2, j+3
+    EndCorr ec;
+    const long eb = plane_offset(G, pl, G.end_per_lev) + lb;
     auto desc = [&](int i, bool store) {
         const long e = (long)i * G.estride;
         const uint8_t c = code[mb + e];
         if (c & CODE_BRESET) { z1 = 0; z2 = 0; z3 = 0; }
         const double4 k = C[cb + e];
-        double v = out[fb + e];
+        double v = k.x * out[fb + e];
+        if (G.endd) v += ec.step(G, eb, i, c, out, fb, true);
         v += k1.y * z1;
         v += k2.z * z2;
         v += k3.w * z3;

@@ -19,7 +19,7 @@ TOL_LINE = 1e-5
 FLOOR = 1e-6
 
 
-def line_errors(gpu, ref):
+def line_errors(gpu, ref, tol_line=TOL_LINE):
     """Worst per-line ratio err / allowed over x-rows and y-columns, and where it is."""
     g = np.asarray(gpu, np.float64)
     r = np.asarray(ref, np.float64)
@@ -33,7 +33,7 @@ def line_errors(gpu, ref):
     worst = (0.0, None)
     for axis, n, name in ((2, nx, "row"), (1, ny, "col")):
         err = np.linalg.norm(d, axis=axis)
-        allowed = TOL_LINE * np.linalg.norm(r, axis=axis) + FLOOR * np.sqrt(n) * rms
+        allowed = tol_line * np.linalg.norm(r, axis=axis) + FLOOR * np.sqrt(n) * rms
         allowed = np.maximum(allowed, 1e-300)
         ratio = err / allowed
         k = np.unravel_index(np.argmax(ratio), ratio.shape)
@@ -42,7 +42,7 @@ def line_errors(gpu, ref):
     return worst
 
 
-def assert_lines(gpu, ref, what=""):
-    ratio, where = line_errors(gpu, ref)
+def assert_lines(gpu, ref, what="", tol_line=TOL_LINE):
+    ratio, where = line_errors(gpu, ref, tol_line)
     assert ratio <= 1.0, f"{what}: line {where} error {ratio:.3g}x its allowance"
     return ratio

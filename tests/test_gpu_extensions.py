@@ -120,3 +120,102 @@ def test_periodic_constant_field_all_sea_uniform_sigma(orc):
         c = torch.full((1, ny, nx), 1.25, dtype=dt, device="cuda")
         out = op.apply_dir(c, "x").double().cpu().numpy()
         np.testing.assert_allclose(out, 1.25 * np.sqrt(2 * np.pi) * s, rtol=tol)
+
+
+# ---------------------------------------------------------------- exact end conditions
+# Per-line FP32 bound with exact ends.  The end correction injects the infinite
+# line's tail, which for large sigma dominates a short segment's output and is a
+# strongly cancelling combination of the end state: an FP32 emulation of the
+# kernels' arithmetic against the oracle gives 1-D errors up to 6.6e-6 on
+# segments of 4-14 points at sigma <= 12 (2.8e-6 on longer ones).  Two such
+# passes (x, y) per line: 3e-5 per line; the field-wide bound stays 1e-5.
+TOL_LINE_END = 3e-5
+# FP64 with exact ends: the oracle and the FP64 kernels both run the printed
+# (direct) recurrence, whose rounding at sigma = 12 is already ~1e-13 without end
+# conditions; the injected tail on segments of a few points adds about one more
+# digit (measured 1.9e-12 between the two on a 50 x 14 grid).  Bound: 1e-11.
+TOL64_END = 1e-11
+
+ECASES = [
+    # seed, ny, nx, nlev, 3-D mask, periodic: tiles x 23 / y 45 (two planes per lane), x 33 / y 56 (one
+    # plane), x 1 / y 1 (one point per lane, one row per wave), a per-level mask (sequential FP32), and
+    # periodic rows with exact ends (sequential FP32)
+    (51, 720, 1440, 3, False, False),
+    (52, 801, 2112, 1, False, False),
+    (53, 14, 50, 2, False, False),
+    (54, 97, 131, 3, False, False),
+    (55, 60, 300, 3, True, False),
+    (56, 40, 500, 2, False, True),
+]
+
+
+@pytest.fixture(scope="module", params=ECASES, ids=lambda c: f"end_s{c[0]}_{c[2]}x{c[1]}x{c[3]}")
+def ecase(request, orc):
+    seed, ny, nx, nlev, m3, per = request.param
+    w = synth.random_case(seed, ny, nx, nlev, 0.3, 4, (1.5, 12.0), 3.0, "fit", m3, False)
+    if per:
+        w = periodic_case(seed, ny, nx, nlev, m3)
+    flags = orc.EXACT_ENDS | (orc.PERIODIC_X if per else 0)
+    P = orc.Problem(w.mask, w.sigma_x, w.sigma_y, n_img=w.n_img, qmode=orc.QMODES[w.qmode], k1=5, flags=flags)
+    op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode, k1=5,
+                              exact_ends=True, periodic_x=per)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((1, nlev, ny, nx))
+    print(f"exact-ends case {w.name} periodic={per}", flush=True)
+    return w, P, op, x
+
+
+def test_exact_ends_fp32(ecase, monkeypatch):
+    """Tiled and line-sequential FP32 paths against the oracle (field-wide 1e-5, per line
+    TOL_LINE_END), and against each other line by line (two independent implementations
+    of the end correction: a slip in either shows as a line far outside rounding)."""
+    w, P, op, x = ecase
+    x32 = x.astype(np.float32)
+    for name, fn, ref in (("forward", op.apply, P.rf3), ("adjoint", op.adjoint, P.rf3_adjoint)):
+        r = ref(x32.astype(np.float64), threads=16)
+        monkeypatch.delenv("RF3_SEQUENTIAL", raising=False)
+        got = fn(torch.from_numpy(x32).cuda()).cpu().numpy()
+        monkeypatch.setenv("RF3_SEQUENTIAL", "1")
+        seq = fn(torch.from_numpy(x32).cuda()).cpu().numpy()
+        monkeypatch.delenv("RF3_SEQUENTIAL")
+        e, es = rel(got, r), rel(seq, r)
+        lr = assert_lines(got, r, f"{w.name} exact ends fp32 {name}", TOL_LINE_END)
+        ls = assert_lines(seq, r, f"{w.name} exact ends fp32 sequential {name}", TOL_LINE_END)
+        lt = assert_lines(got, seq, f"{w.name} exact ends tiled vs sequential {name}", TOL_LINE_END)
+        print(f"  fp32 {name}: rel {e:.2e} (sequential {es:.2e}); worst line {lr:.3f} / {ls:.3f} "
+              f"(tiled vs sequential {lt:.3f}) of allowance", flush=True)
+        assert e <= TOL32 and es <= TOL32
+
+
+def test_exact_ends_fp64(ecase):
+    w, P, op, x = ecase
+    xd = torch.from_numpy(x).cuda()
+    ef = rel(op.apply(xd).cpu().numpy(), P.rf3(x, threads=16))
+    ea = rel(op.adjoint(xd).cpu().numpy(), P.rf3_adjoint(x, threads=16))
+    print(f"  fp64: forward {ef:.2e}, adjoint {ea:.2e}", flush=True)
+    assert ef <= TOL64_END and ea <= TOL64_END
+
+
+def test_exact_ends_leave_rf1_and_differ_from_zero_ends(ecase):
+    w, P, op, x = ecase
+    per = bool(P.flags & 1)
+    op0 = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode, k1=5,
+                               periodic_x=per)
+    xd = torch.from_numpy(x).cuda()
+    assert torch.equal(op.rf1(xd, K=5), op0.rf1(xd, K=5))
+    x32 = xd.float()
+    assert not torch.equal(op.apply(x32), op0.apply(x32))
+
+
+def test_exact_ends_uniform_sigma_diagonal_is_flat_on_the_gpu():
+    """Uniform sigma, one all-sea row: with exact ends the x operator's diagonal is the same at
+    both ends of the row as inside it (FP64 path)."""
+    nx, s = 61, 4.0
+    mask = np.ones((1, 1, nx), np.uint8)
+    sig = np.full((1, 1, nx), s)
+    op = HorizontalCovariance(mask, sig, sig, 1, n_img=0, qmode="fit", exact_ends=True)
+    E = torch.eye(nx, dtype=torch.float64, device="cuda").reshape(nx, 1, 1, nx)
+    G = op.apply_dir(E, "x").reshape(nx, nx).cpu().numpy().T
+    d = np.diag(G)
+    assert np.ptp(d) <= 1e-12 * d.max()
+    np.testing.assert_allclose(G, G.T, atol=1e-12 * d.max())

@@ -104,6 +104,39 @@ def bench_batch(torch, dev, args):
     return res
 
 
+def bench_variants(torch, dev, args):
+    """C3 step (forward + adjoint) with the options beyond the paper's scheme: zonally periodic
+    rows, exact end conditions, and anisotropic inhomogeneous length scales (same field)."""
+    from paper_1404_5756_amd import synth
+    from paper_1404_5756_amd.operator import HorizontalCovariance
+    res = {}
+    base = synth.c3_global()
+    x = torch.from_numpy(base.field(np.float32)).to(dev)
+    out = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, w, kw in (("periodic_x", base, {"periodic_x": True}), ("exact_ends", base, {"exact_ends": True}),
+                        ("anisotropic", synth.c3_anisotropic(), {})):
+        op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode, device=dev,
+                                  **kw)
+        for _ in range(5):
+            op.apply(x, out=out)
+            op.adjoint(x, out=out)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            op.apply(x, out=out)
+            op.adjoint(x, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res[name] = {"ms_fwd_adj": round(ms, 4), "gpoints_s": round(w.points / (ms * 1e-3) / 1e9, 2)}
+        log(f"variant {name}: fwd+adj {ms:.3f} ms -> {res[name]['gpoints_s']} Gpoints/s")
+        del op
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_cg(torch, dev, w, op, args):
     """3D-VAR CG iterations (C5) on the C3 grid with 200k bilinear observations, FP32."""
     from paper_1404_5756_amd.var3d import synthetic_problem
@@ -251,6 +284,7 @@ def main():
     out_f.copy_(x)
     torch.cuda.synchronize()
 
+    variants = bench_variants(torch, dev, args)
     batch = None if args.no_batch else bench_batch(torch, dev, args)
     cg = None if args.no_cg else bench_cg(torch, dev, w, op, args)
 
@@ -299,6 +333,7 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "rf3_fwd_ms": round(ms_fwd, 4),
         "rf1_fp64_k5": rf1,
+        "c3_variants": variants,
         "batch_c4": batch,
         "cg_c5": cg,
         "parity_sample": parity,

@@ -97,6 +97,25 @@ def c3_global(nlev=50):
     return Workload("c3_1440x720x50", nx, ny, nlev, 1, mask, s[None], s[None].copy(), seed=seed)
 
 
+def c3_anisotropic(nlev=50):
+    """The C3 grid with anisotropic, spatially inhomogeneous length scales (Sec. 5: tropical
+    scales up to ~350 km, i.e. ~12 grid points at 1/4 deg, with zonal correlations longer than
+    meridional ones there): zonal sigma_x = 1.5 + 10.5 cos^2(latitude) as in C3, meridional
+    sigma_y = sigma_x / (1 + exp(-(lat/15 deg)^2)) (half the zonal scale at the equator, equal
+    at high latitude), and a patch of short scales (x 0.4) standing for a western boundary
+    current such as the Kuroshio Extension."""
+    w = c3_global(nlev)
+    nx, ny = w.nx, w.ny
+    lat = -90.0 + (np.arange(ny) + 0.5) * 0.25
+    sx = w.sigma_x[0].copy()
+    sy = sx / (1.0 + np.exp(-(lat / 15.0) ** 2))[:, None]
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    patch = np.exp(-(((ii - 0.38 * nx) / (0.05 * nx)) ** 2 + ((jj - 0.65 * ny) / (0.04 * ny)) ** 2))
+    scale = 1.0 - 0.6 * patch
+    return Workload("c3_aniso_1440x720x50", nx, ny, nlev, 1, w.mask, (sx * scale)[None], (sy * scale)[None],
+                    seed=w.seed)
+
+
 def c4_batch(nitems=64):
     """64 grids with nx~U[128,1024], ny~U[128,768], nlev~U[1,75], land~U[0.1,0.5], sigma in [2, 8]."""
     seed = SEEDS["c4"]

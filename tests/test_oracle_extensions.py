@@ -297,3 +297,61 @@ def test_periodic_is_x_only_and_2d_is_rows_then_columns(orc):
     np.testing.assert_array_equal(Gy, Gy0)
     V = np.stack([P.rf3(E[k]).ravel() for k in range(N)], axis=1)
     np.testing.assert_allclose(V, Gy @ Gx, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------- anisotropic, inhomogeneous scales
+@pytest.mark.parametrize("sx,sy", [(2.0, 5.0), (7.0, 3.0)])
+def test_anisotropic_impulse_moments(orc, sx, sy):
+    """sigma_x != sigma_y (VARMATCH): the 2-D impulse response is separable with second moments
+    exactly sigma_x^2 along x and sigma_y^2 along y, no cross moment, mass 2 pi sigma_x sigma_y."""
+    ny, nx = int(48 * sy) | 1, int(48 * sx) | 1
+    P = orc.Problem(np.ones((ny, nx)), np.full((ny, nx), sx), np.full((ny, nx), sy), qmode=orc.VARMATCH)
+    imp = np.zeros((ny, nx))
+    imp[ny // 2, nx // 2] = 1.0
+    h = P.rf3(imp)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    yy, xx = yy - ny // 2, xx - nx // 2
+    m = h.sum()
+    assert m == pytest.approx(2 * np.pi * sx * sy, rel=1e-7)
+    assert (h * xx * xx).sum() / m == pytest.approx(sx * sx, rel=1e-6)
+    assert (h * yy * yy).sum() / m == pytest.approx(sy * sy, rel=1e-6)
+    assert abs((h * xx * yy).sum() / m) < 1e-9 * sx * sy
+    # separable: the response is the outer product of the two 1-D responses
+    np.testing.assert_allclose(h, np.outer(h[:, nx // 2], h[ny // 2, :]) / h[ny // 2, nx // 2], rtol=1e-10,
+                               atol=1e-14 * h.max())
+
+
+def test_inhomogeneous_anisotropic_covariance_is_symmetric_psd(orc):
+    """Spatially varying sigma_x != sigma_y with land: V is not symmetric, but the covariance
+    B = V V^T it models is symmetric positive semi-definite (dense, tiny grid)."""
+    rng = np.random.default_rng(110)
+    ny, nx = 9, 11
+    mask = (rng.uniform(size=(ny, nx)) > 0.2).astype(np.uint8)
+    sx = rng.uniform(1.5, 6.0, (ny, nx))
+    sy = 0.5 * sx + rng.uniform(0.5, 1.0, (ny, nx))
+    P = orc.Problem(mask, sx, sy, n_img=2, qmode=orc.FIT)
+    N = ny * nx
+    E = np.eye(N).reshape(N, ny, nx)
+    V = np.stack([P.rf3(E[k]).ravel() for k in range(N)], axis=1)
+    Vt = np.stack([P.rf3_adjoint(E[k]).ravel() for k in range(N)], axis=1)
+    np.testing.assert_allclose(Vt, V.T, rtol=1e-12, atol=1e-13 * np.abs(V).max())
+    assert np.abs(V - V.T).max() > 1e-3
+    B = V @ Vt
+    np.testing.assert_allclose(B, B.T, rtol=1e-12, atol=1e-12 * np.abs(B).max())
+    assert np.linalg.eigvalsh(B).min() > -1e-10 * np.abs(B).max()
+
+
+def test_inhomogeneous_local_width_follows_the_local_scale(orc):
+    """Slowly varying sigma_x along a line (VARMATCH): the impulse response at a point has a
+    second moment close to the local sigma^2 (a 1.2% per grid point gradient moves it by a few %)."""
+    n = 1201
+    i = np.arange(n)
+    sig = 6.0 * np.exp(0.012 * (i - n // 2) / 6.0)          # +-20% over +-100 points
+    P = orc.Problem(np.ones((1, n)), sig[None], sig[None], qmode=orc.VARMATCH)
+    for c in (450, 600, 750):
+        x = np.zeros((1, n))
+        x[0, c] = 1.0
+        h = P.apply_dir(x, "x")[0]
+        k = i - c
+        var = (h * k * k).sum() / h.sum()
+        assert var == pytest.approx(sig[c] ** 2, rel=0.05)

@@ -104,6 +104,49 @@ def bench_batch(torch, dev, args):
     return res
 
 
+def k_frontier(torch, dev, w, x, ms_rf3_fwd, args):
+    """Accuracy/time frontier of the 1st-RF over K against the 3rd-RF (the GPU analogue of the
+    paper's K = 1, 5, 10 comparison): time of the fused FP32 1st-RF on the workload for each K, and
+    the Gaussian shape error of the GPU impulse response on an all-sea line (sigma = 4 and 12):
+    || h/sum h - g/sum g || / || g/sum g || with g the Gaussian of width sigma."""
+    from paper_1404_5756_amd.operator import HorizontalCovariance
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = torch.empty_like(x)
+
+    def shape_err(sig, K=None):
+        n = int(60 * sig) | 1
+        mask = np.ones((1, 1, n), np.uint8)
+        s = np.full((1, 1, n), float(sig))
+        op1 = HorizontalCovariance(mask, s, s, 1, n_img=0, qmode="fit", k1=K or 1, device=dev)
+        imp = torch.zeros((1, 1, n), dtype=torch.float64, device=dev)
+        imp[0, 0, n // 2] = 1.0
+        h = (op1.rf1_fused(imp, K=K) if K else op1.apply_dir(imp, "x")).cpu().numpy().ravel()
+        i = np.arange(n) - n // 2
+        g = np.exp(-i * i / (2.0 * sig * sig))
+        hn, gn = h / h.sum(), g / g.sum()
+        return float(np.linalg.norm(hn - gn) / np.linalg.norm(gn))
+
+    res = {"rf3_fit": {"ms_fwd": round(ms_rf3_fwd, 4), "shape_err_sigma4": round(shape_err(4.0), 4),
+                       "shape_err_sigma12": round(shape_err(12.0), 4)}}
+    for K in (1, 2, 3, 5, 10):
+        op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode, k1=K,
+                                  device=dev)
+        op.rf1_fused(x, K=K, out=out)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(5):
+            op.rf1_fused(x, K=K, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        res[f"rf1_k{K}"] = {"ms_fused_fp32": round(ms, 4), "shape_err_sigma4": round(shape_err(4.0, K), 4),
+                            "shape_err_sigma12": round(shape_err(12.0, K), 4)}
+        del op
+    log("K frontier: " + ", ".join(f"{k} {v}" for k, v in res.items()))
+    return res
+
+
 def bench_variants(torch, dev, args):
     """C3 step (forward + adjoint) with the options beyond the paper's scheme: zonally periodic
     rows, exact end conditions, and anisotropic inhomogeneous length scales (same field)."""
@@ -274,10 +317,27 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms_rf1 = e0.elapsed_time(e1) / r1reps
+        # fused 1st-RF: all K iterations of a direction on chip (FP64 and FP32)
+        def timed_rf1(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+        ms_f64 = timed_rf1(lambda: op.rf1_fused(x64, K=5, out=o64))
+        o32 = torch.empty_like(x)
+        ms_f32 = timed_rf1(lambda: op.rf1_fused(x, K=5, out=o32))
         rf1 = {"ms": round(ms_rf1, 3), "gpoints_s": round(pts / (ms_rf1 * 1e-3) / 1e9, 2),
-               "speedup_rf3_fp32_fwd_vs_rf1_fp64_k5": round(ms_rf1 / ms_fwd, 2)}
-        log(f"1st-RF FP64 K=5: {ms_rf1:.3f} ms; 3rd-RF FP32 forward {ms_fwd:.3f} ms")
-        del x64, o64
+               "speedup_rf3_fp32_fwd_vs_rf1_fp64_k5": round(ms_rf1 / ms_fwd, 2),
+               "fused_fp64_ms": round(ms_f64, 3), "speedup_rf3_fp32_fwd_vs_fused_rf1_fp64_k5": round(ms_f64 / ms_fwd, 2),
+               "fused_fp32_ms": round(ms_f32, 3), "speedup_rf3_fp32_fwd_vs_fused_rf1_fp32_k5": round(ms_f32 / ms_fwd, 2)}
+        log(f"1st-RF K=5: plain FP64 {ms_rf1:.3f} ms, fused FP64 {ms_f64:.3f} ms, fused FP32 {ms_f32:.3f} ms; "
+            f"3rd-RF FP32 forward {ms_fwd:.3f} ms")
+        rf1["k_frontier"] = k_frontier(torch, dev, w, x, ms_fwd, args)
+        del x64, o64, o32
 
     # ---- a plain copy of the field (known bytes): the reference that scales the
     # FETCH_SIZE / WRITE_SIZE counters of a rocprofv3 run of this script

@@ -147,6 +147,18 @@ int rf3_apply_dir(const rf_grid *g, const void *coef, rf_prec prec, int32_t dir,
 int rf1_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, int32_t K,
                  const void *in, void *out, int32_t nlev, int32_t nfields, void *stream);
 
+/* The same operator as rf1_apply_xy, fused: all K iterations along x in one
+ * kernel and all K along y in a second, each line kept on chip between
+ * iterations (the field crosses HBM once per direction, not once per
+ * iteration; the sweeps of a line are chunked and joined by scans).  FP32 or
+ * FP64.  Results equal rf1_apply_xy up to rounding.  This is the fast 1st-RF
+ * the 3rd-RF is compared with (the paper compares with its 1st-RF at K = 1, 5,
+ * 10, Sec. 4.1, 5.1).  RF_E_UNSUPPORTED for grids whose mask or sigma vary
+ * with level, periodic rows, or rows/columns longer than the tiled kernels
+ * take (nx > 2112, ny > 1024); rf1_apply_xy covers those. */
+int rf1_apply_xy_fused(const rf_grid *g, const void *coef, rf_prec prec, int32_t K,
+                       const void *in, void *out, int32_t nlev, int32_t nfields, void *stream);
+
 /* Many independent fields on possibly different grids in one pass (T and S
  * on every level of several grids: the paper runs the levels of its global
  * configuration in parallel, Sec. 5.1).  Each item applies rf3_apply_xy

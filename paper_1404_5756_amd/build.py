@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librf3.so")
-SOURCES = ["coef.hip", "sweep_seq.hip", "sweep_fast.hip", "batch.hip", "obs.hip", "cg.hip", "abi.hip"]
+SOURCES = ["coef.hip", "sweep_seq.hip", "sweep_fast.hip", "rf1_fast.hip", "batch.hip", "obs.hip", "cg.hip",
+           "abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -177,6 +177,26 @@ extern "C" int rf1_apply_xy(const rf_grid *g, const void *coef, rf_prec prec, in
     return e == hipSuccess ? RF_OK : RF_E_HIP;
 }
 
+extern "C" int rf1_apply_xy_fused(const rf_grid *g, const void *coef, rf_prec prec, int32_t K, const void *in,
+                                  void *out, int32_t nlev, int32_t nfields, void *stream)
+{
+    const int rc = check_apply(g, coef, prec, in, out, nlev, nfields);
+    if (rc) return rc;
+    if (K != g->k1 || K < 1) return RF_E_ARG;
+    const BlockHeader h = layout(g);
+    if (g->mask_nlev != 1 || g->sigma_nlev != 1 || !h.lx || !h.ly || (g->flags & RF_PERIODIC_X))
+        return RF_E_UNSUPPORTED;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int nplanes = nlev * nfields;
+    hipError_t e = fused_rf1(in, out, prec == RF_FP64, tab<double2>(coef, h.off_r1[0]), tab<uint64_t>(coef, h.off_lmx),
+                             0, h.lx, g->nx, g->ny, nplanes, K, st);
+    if (e == hipSuccess)
+        e = fused_rf1(out, out, prec == RF_FP64, tab<double2>(coef, h.off_r1[1]), tab<uint64_t>(coef, h.off_lmy), 1,
+                      h.ly, g->nx, g->ny, nplanes, K, st);
+    if (e == hipErrorNotSupported) return RF_E_UNSUPPORTED;
+    return e == hipSuccess ? RF_OK : RF_E_HIP;
+}
+
 extern "C" const char *rf_strerror(int status)
 {
     switch (status) {

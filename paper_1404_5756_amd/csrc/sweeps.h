@@ -43,6 +43,9 @@ hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits,
 int x_groups(int ny, int nplanes, int gmax);
 hipError_t setup_phi_y(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int ly, hipStream_t st);
 hipError_t setup_ky_y(const float4 *T, const uint8_t *code, float *KY, int nx, int ny, int ly, hipStream_t st);
+// fused 1st-RF (rf1_fast.hip): K iterations of one direction on chip; l = lx (dir 0) or ly (dir 1)
+hipError_t fused_rf1(const void *in, void *out, bool fp64, const double2 *C, const uint64_t *LM, int dir, int l,
+                     int nx, int ny, int nplanes, int K, hipStream_t st);
 hipError_t setup_phi_x(const float4 *T, const uint8_t *code, float *PHI, int nx, int ny, int lx, hipStream_t st);
 hipError_t setup_per_x(const float4 *T, const uint8_t *code, float *PER, int nx, int ny, int lx, hipStream_t st);
 }  // namespace rf

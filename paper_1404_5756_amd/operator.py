@@ -100,6 +100,16 @@ class HorizontalCovariance:
         return out
 
 
+    def rf1_fused(self, x, K=None, out=None, stream=None):
+        """1st-RF with all K iterations of a direction on chip (FP32 or FP64)."""
+        x = x.contiguous()
+        out = torch.empty_like(x) if out is None else out
+        nf, nl = self._shape(x)
+        rf3.rf1_apply_xy_fused(self.grid, self.coef, self._prec(x), self.grid.k1 if K is None else K, x, out,
+                               nl, nf, stream)
+        return out
+
+
 class Batch:
     """Several (operator, input, output) items applied together (rf3_apply_batch).
 

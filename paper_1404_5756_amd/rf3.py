@@ -74,6 +74,8 @@ def lib() -> ctypes.CDLL:
         L.rf3_apply_dir.argtypes = [G, P, I, I, I, P, P, I, I, P]
         L.rf1_apply_xy.restype = I
         L.rf1_apply_xy.argtypes = [G, P, I, I, P, P, I, I, P]
+        L.rf1_apply_xy_fused.restype = I
+        L.rf1_apply_xy_fused.argtypes = [G, P, I, I, P, P, I, I, P]
         L.rf3_batch_plan_bytes.restype = S
         L.rf3_batch_plan_bytes.argtypes = [B, I]
         L.rf3_batch_plan.restype = I
@@ -182,6 +184,11 @@ def rf3_apply_dir(g, coef, prec, direction, adjoint, inp, out, nlev, nfields, st
 def rf1_apply_xy(g, coef, prec, K, inp, out, nlev, nfields, stream=None):
     _check(lib().rf1_apply_xy(ctypes.byref(g), _ptr(coef), int(prec), int(K), _ptr(inp), _ptr(out),
                               int(nlev), int(nfields), _stream(stream)), "rf1_apply_xy")
+
+
+def rf1_apply_xy_fused(g, coef, prec, K, inp, out, nlev, nfields, stream=None):
+    _check(lib().rf1_apply_xy_fused(ctypes.byref(g), _ptr(coef), int(prec), int(K), _ptr(inp), _ptr(out),
+                                    int(nlev), int(nfields), _stream(stream)), "rf1_apply_xy_fused")
 
 
 def _items(items):

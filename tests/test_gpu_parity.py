@@ -242,3 +242,25 @@ def test_c1_impulse_and_noise(orc, qmode):
     # impulse response of the 2-D filter peaks at the impulse with ~2 pi sigma^2 mass
     h = op.apply(torch.from_numpy(w.extra["impulse"]).cuda()).cpu().numpy()[0, 0]
     assert np.unravel_index(np.argmax(h), h.shape) == (32, 32)
+
+
+def test_rf1_fused(case):
+    """Fused 1st-RF (all K iterations of a direction on chip) against the oracle: FP64 to 1e-12,
+    FP32 to 1e-5 and line by line; shapes outside the tiled kernels report RF_E_UNSUPPORTED."""
+    w, x, P, _, _, op = case
+    tiled = w.mask.shape[0] == 1 and w.sigma_x.shape[0] == 1 and w.nx <= 2112 and w.ny <= 1024
+    if not tiled:
+        with pytest.raises(rf3.RFError) as e:
+            op.rf1_fused(torch.from_numpy(x).cuda(), K=5)
+        assert e.value.status == rf3.RF_E_UNSUPPORTED
+        return
+    ref = P.rf1(x, K=5)
+    out = op.rf1_fused(torch.from_numpy(x).cuda(), K=5).cpu().numpy()
+    assert rel(out, ref) <= TOL64
+    x32 = x.astype(np.float32)
+    ref32 = P.rf1(x32.astype(np.float64), K=5)
+    out32 = op.rf1_fused(torch.from_numpy(x32).cuda(), K=5).cpu().numpy()
+    e = rel(out32, ref32)
+    r = assert_lines(out32, ref32, f"{w.name} fused 1st-RF fp32")
+    print(f"case {w.name} fused 1st-RF: fp32 rel {e:.2e}, worst line {r:.3f}", flush=True)
+    assert e <= TOL32

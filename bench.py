@@ -219,6 +219,8 @@ def main():
     ap.add_argument("--no-rf1", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-grid batch (C4)")
     ap.add_argument("--no-cg", action="store_true", help="skip the 3D-VAR CG iterations (C5)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the periodic / exact-end / anisotropic C3 variants")
     ap.add_argument("--cg-iters", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -247,6 +249,46 @@ def main():
     pts = w.points
     stream = torch.cuda.current_stream()
 
+    # ---- per-kernel times, in the step's own order and data flow (rf3_apply_xy is
+    # x: x -> out then y: out -> out; rf3_adjoint_xy is y then x), one event between
+    # launches; each call of rf3_apply_dir is one kernel launch
+    reps = max(5, args.steps)
+    seq = (("x_fwd", 0, False, x, out_f), ("y_fwd", 1, False, out_f, out_f),
+           ("y_adj", 1, True, x, out_a), ("x_adj", 0, True, out_a, out_a))
+    # its own warm-up (the GPU's clocks settle over the first ~100 ms of work)
+    for _ in range(max(50, reps)):
+        for name, d, adj, src, dst in seq:
+            op.apply_dir(src, d, adj, out=dst)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(seq) + 1)] for _ in range(reps)]
+    for r in range(reps):
+        evs[r][0].record(stream)
+        for k, (name, d, adj, src, dst) in enumerate(seq):
+            op.apply_dir(src, d, adj, out=dst)
+            evs[r][k + 1].record(stream)
+    torch.cuda.synchronize()
+    kern = {name: sum(evs[r][k].elapsed_time(evs[r][k + 1]) for r in range(reps)) / reps
+            for k, (name, *_rest) in enumerate(seq)}
+    log("kernel ms: " + ", ".join(f"{k} {v:.3f}" for k, v in kern.items()))
+    # the same launches with the last-level (Infinity) cache flushed before each one:
+    # 1 GiB written between launches evicts the 256 MB MALL, so the kernel reads its
+    # field and tables from HBM (the in-step times above can be partly cache-served)
+    flush = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(len(seq))]
+    kern_flushed = {name: 0.0 for name, *_r in seq}
+    freps = max(3, reps // 5)
+    for r in range(freps):
+        for k, (name, d, adj, src, dst) in enumerate(seq):
+            flush.fill_(float(r + k))
+            ev2[k][0].record(stream)
+            op.apply_dir(src, d, adj, out=dst)
+            ev2[k][1].record(stream)
+        torch.cuda.synchronize()
+        for k, (name, *_r) in enumerate(seq):
+            kern_flushed[name] += ev2[k][0].elapsed_time(ev2[k][1]) / freps
+    del flush
+    torch.cuda.empty_cache()
+    log("kernel ms, cache flushed between launches: " + ", ".join(f"{k} {v:.3f}" for k, v in kern_flushed.items()))
     # ---- the step: forward + adjoint
     for _ in range(args.warmup):
         op.apply(x, out=out_f)
@@ -263,25 +305,6 @@ def main():
     value = pts / (ms_step * 1e-3) / 1e9
     log(f"step (fwd+adj): {ms_step:.3f} ms -> {value:.1f} Gpoints/s")
 
-    # ---- per-kernel times, in the step's own order and data flow (rf3_apply_xy is
-    # x: x -> out then y: out -> out; rf3_adjoint_xy is y then x), one event between
-    # launches; each call of rf3_apply_dir is one kernel launch
-    reps = max(5, args.steps)
-    seq = (("x_fwd", 0, False, x, out_f), ("y_fwd", 1, False, out_f, out_f),
-           ("y_adj", 1, True, x, out_a), ("x_adj", 0, True, out_a, out_a))
-    for name, d, adj, src, dst in seq:
-        op.apply_dir(src, d, adj, out=dst)
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(seq) + 1)] for _ in range(reps)]
-    for r in range(reps):
-        evs[r][0].record(stream)
-        for k, (name, d, adj, src, dst) in enumerate(seq):
-            op.apply_dir(src, d, adj, out=dst)
-            evs[r][k + 1].record(stream)
-    torch.cuda.synchronize()
-    kern = {name: sum(evs[r][k].elapsed_time(evs[r][k + 1]) for r in range(reps)) / reps
-            for k, (name, *_rest) in enumerate(seq)}
-    log("kernel ms: " + ", ".join(f"{k} {v:.3f}" for k, v in kern.items()))
     dom = max(kern, key=kern.get)
     bytes_per_launch = 8.0 * pts        # FP32 read + write of every point once
     achieved = bytes_per_launch / (kern[dom] * 1e-3) / 1e9
@@ -292,9 +315,12 @@ def main():
         src_hash = kernel_code_hash()
         if tf.get("kernel_code_sha256") == src_hash and dom in tf.get("bytes_per_launch", {}):
             traffic = tf["bytes_per_launch"][dom]
+    achieved_flushed = bytes_per_launch / (kern_flushed[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "achieved_cache_flushed": round(achieved_flushed, 1),
+                "frac_cache_flushed": round(achieved_flushed / HBM_PEAK_GBS, 4)}
     step_frac = 4 * bytes_per_launch / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
     # ---- forward alone and the FP64 1st-RF baseline (K = 5), same grid and field
@@ -344,7 +370,7 @@ def main():
     out_f.copy_(x)
     torch.cuda.synchronize()
 
-    variants = bench_variants(torch, dev, args)
+    variants = None if args.no_variants else bench_variants(torch, dev, args)
     batch = None if args.no_batch else bench_batch(torch, dev, args)
     cg = None if args.no_cg else bench_cg(torch, dev, w, op, args)
 
@@ -370,6 +396,15 @@ def main():
                "kind": "oracle", "seconds": round(cpu_s, 2),
                "sample": f"fwd+adj V_H of {nl} of {w.nlev} levels ({sample_pts / 1e6:.2f} M points), FP64 C oracle, "
                          f"OpenMP over lines, median of 3 runs"}
+        # the same oracle on one thread, on 5 levels
+        n1 = min(5, nl)
+        t0 = time.time()
+        P.rf3(xs[:, :n1], threads=1)
+        P.rf3_adjoint(xs[:, :n1], threads=1)
+        t1s = time.time() - t0
+        cpu["one_thread"] = {"value": round(w.nx * w.ny * n1 / t1s / 1e9, 5), "unit": "Gpoints/s",
+                             "seconds": round(t1s, 2), "sample": f"fwd+adj V_H of {n1} levels, 1 thread"}
+        log(f"cpu oracle on 1 thread: {t1s:.2f} s for {n1} levels")
         op.apply(x, out=out_f)
         op.adjoint(x, out=out_a)
         torch.cuda.synchronize()
@@ -391,6 +426,7 @@ def main():
         "cpu_baseline": cpu,
         "hbm_frac_step": round(step_frac, 4),
         "kernel_ms": {k: round(v, 4) for k, v in kern.items()},
+        "kernel_ms_cache_flushed": {k: round(v, 4) for k, v in kern_flushed.items()},
         "rf3_fwd_ms": round(ms_fwd, 4),
         "rf1_fp64_k5": rf1,
         "c3_variants": variants,

@@ -234,7 +234,9 @@ int rf3_apply_batch_ex(const rf_batch_item *items, int32_t n, const rf_batch_tun
  *     observation reads it).  Deterministic: each point sums its entries in
  *     observation order, without atomics.
  * nobs, nuniq and npts = nx*ny*nlev must be the plan's; otherwise the kernels
- * read nothing (and rf_obs_adjoint leaves a zero field).  Asynchronous on
+ * read nothing past the plan header and set every output to NaN (the plan
+ * lives in device memory, so the mismatch is detected on the device and shows
+ * in the results, not in the return code).  Asynchronous on
  * `stream`, no allocation; obs and field are device arrays of `prec`. */
 size_t rf_obs_plan_bytes(const rf_grid *g, int32_t nobs, const int32_t *lev, const double *x, const double *y,
                          int32_t *nuniq_out);

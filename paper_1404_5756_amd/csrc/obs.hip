@@ -100,11 +100,15 @@ int build(const rf_grid *g, int32_t nobs, const int32_t *lev, const double *x, c
     return RF_OK;
 }
 
-// the plan's own sizes must equal the launch sizes, else nothing is read
+// the plan's own sizes must equal the launch sizes; otherwise nothing past the
+// plan header is read and every output is set to NaN (a visible failure rather
+// than a silently zero or partial result)
 __device__ inline bool plan_matches(const ObsPlanHeader *hd, int32_t nobs, int32_t nuniq, int64_t npts)
 {
     return hd->magic == kObsMagic && hd->nobs == nobs && hd->nuniq == nuniq && hd->npts == npts;
 }
+template <class T>
+__device__ inline T nan_value() { return (T)__builtin_nan(""); }
 
 template <class T>
 __global__ void k_obs_apply(const ObsPlanHeader *__restrict__ hd, const int32_t *__restrict__ idx,
@@ -112,7 +116,11 @@ __global__ void k_obs_apply(const ObsPlanHeader *__restrict__ hd, const int32_t 
                             int32_t nuniq, int64_t npts)
 {
     const int32_t o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= nobs || !plan_matches(hd, nobs, nuniq, npts)) return;
+    if (o >= nobs) return;
+    if (!plan_matches(hd, nobs, nuniq, npts)) {
+        out[o] = nan_value<T>();
+        return;
+    }
     T s = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) s += (T)w[4 * o + c] * f[idx[4 * o + c]];
@@ -127,7 +135,12 @@ __global__ void k_obs_innov(const ObsPlanHeader *__restrict__ hd, const int32_t 
                             int32_t nobs, int32_t nuniq, int64_t npts)
 {
     const int32_t o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= nobs || !plan_matches(hd, nobs, nuniq, npts)) return;
+    if (o >= nobs) return;
+    if (!plan_matches(hd, nobs, nuniq, npts)) {
+        if (d) d[o] = nan_value<T>();
+        rd[o] = nan_value<T>();
+        return;
+    }
     T s = 0;
     if (f) {
 #pragma unroll
@@ -141,15 +154,20 @@ __global__ void k_obs_innov(const ObsPlanHeader *__restrict__ hd, const int32_t 
 // f[0, n) = 0: 16-byte stores over the first nv 16-byte elements (nv is 0 when
 // f is not 16-byte aligned), then single entries.  Streamed once, so the stores
 // are non-temporal and leave L2 to the covariance operator's tables.
+// (NaN instead of 0 when the plan does not match the launch sizes)
 template <class T>
-__global__ void k_fill(T *__restrict__ f, long n, long nv)
+__global__ void k_fill(T *__restrict__ f, long n, long nv, const ObsPlanHeader *__restrict__ hd, int32_t nobs,
+                       int32_t nuniq)
 {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const long t0 = (long)blockIdx.x * blockDim.x + threadIdx.x, stride = (long)gridDim.x * blockDim.x;
+    const T val = plan_matches(hd, nobs, nuniq, n) ? (T)0 : nan_value<T>();
     u32x4 *fv = reinterpret_cast<u32x4 *>(f);
-    const u32x4 z = {0u, 0u, 0u, 0u};
+    T vv[16 / sizeof(T)];
+    for (int q = 0; q < (int)(16 / sizeof(T)); ++q) vv[q] = val;
+    const u32x4 z = *reinterpret_cast<const u32x4 *>(vv);
     for (long i = t0; i < nv; i += stride) __builtin_nontemporal_store(z, fv + i);
-    for (long i = nv * (long)(16 / sizeof(T)) + t0; i < n; i += stride) __builtin_nontemporal_store((T)0, f + i);
+    for (long i = nv * (long)(16 / sizeof(T)) + t0; i < n; i += stride) __builtin_nontemporal_store(val, f + i);
 }
 
 template <class T>
@@ -252,11 +270,11 @@ extern "C" int rf_obs_adjoint(const void *plan_dev, int32_t nobs, int32_t nuniq,
     const long es = prec == RF_FP32 ? 4 : 8;
     const long nv = reinterpret_cast<uintptr_t>(field) % 16 ? 0 : npts * es / 16;
     if (prec == RF_FP32) {
-        k_fill<float><<<nf, 256, 0, st>>>((float *)field, npts, nv);
+        k_fill<float><<<nf, 256, 0, st>>>((float *)field, npts, nv, hd, nobs, nuniq);
         k_obs_adjoint<float><<<nb, 256, 0, st>>>(hd, upt, uptr, ent, w, (const float *)obs, (float *)field, nobs,
                                                  nuniq, npts);
     } else {
-        k_fill<double><<<nf, 256, 0, st>>>((double *)field, npts, nv);
+        k_fill<double><<<nf, 256, 0, st>>>((double *)field, npts, nv, hd, nobs, nuniq);
         k_obs_adjoint<double><<<nb, 256, 0, st>>>(hd, upt, uptr, ent, w, (const double *)obs, (double *)field, nobs,
                                                   nuniq, npts);
     }

@@ -230,3 +230,28 @@ def test_cg_vector_kernels(dtype, offset):
     X, Y = (t.double().cpu().numpy() for t in (x, y))
     rf3.rf_axpy(prec, n, -0.75, x, y)
     assert rel(y.double().cpu().numpy(), Y - 0.75 * X) < tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_mismatched_plan_gives_nan_outputs(grid, dtype):
+    """Launch sizes that are not the plan's: H, H^T and the innovation write NaN everywhere
+    instead of returning a silently zero or partial result."""
+    from paper_1404_5756_amd import rf3
+    w, op, lev, xs, ys = grid
+    obs = Observations(op, lev, xs, ys)
+    prec = rf3.RF_FP32 if dtype == torch.float32 else rf3.RF_FP64
+    f = torch.randn(obs.shape, device=DEV, dtype=dtype)
+    d = torch.randn(obs.nobs, device=DEV, dtype=dtype)
+    n1 = obs.nobs - 1
+    out = torch.zeros(n1, device=DEV, dtype=dtype)
+    rf3.rf_obs_apply(obs.plan, n1, obs.nuniq, obs.npts, prec, f, out)
+    assert torch.isnan(out).all()
+    fld = torch.zeros(obs.shape, device=DEV, dtype=dtype)
+    rf3.rf_obs_adjoint(obs.plan, obs.nobs, obs.nuniq + 1, obs.npts, prec, d, fld)
+    assert torch.isnan(fld).all()
+    rd = torch.zeros(obs.nobs, device=DEV, dtype=dtype)
+    rf3.rf_obs_innovation(obs.plan, obs.nobs, obs.nuniq, obs.npts - 1, prec, f, d, None, 1.0, None, rd)
+    assert torch.isnan(rd).all()
+    # the matching sizes still work after a mismatched call
+    good = obs.apply(f)
+    assert torch.isfinite(good).all()

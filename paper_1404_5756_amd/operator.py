@@ -152,11 +152,29 @@ class Batch:
         rf3.rf3_apply_batch(self._items, rf3.RF_FP32, int(bool(adjoint)), self.plan, self.plan.numel(), stream,
                             self.tuning)
 
-    def autotune(self, candidates=None, reps=3):
+    # autotune results per (device architecture, CU count, item shapes): a batch of
+    # the same shapes on the same kind of device reuses the shape found before
+    _tuned = {}
+
+    def signature(self):
+        """(architecture, CUs, sorted item shapes and flags): what the best work-list shape depends on."""
+        props = torch.cuda.get_device_properties(self.device)
+        arch = getattr(props, "gcnArchName", props.name)
+        shapes = tuple(sorted((g.nx, g.ny, g.nlev, g.mask_nlev, g.sigma_nlev, g.flags, int(nf))
+                              for g, _c, _x, _y, nf in self._items))
+        return (arch, props.multi_processor_count, shapes)
+
+    def autotune(self, candidates=None, reps=3, cache=True):
         """Time forward + adjoint for each candidate work-list shape on these items
         and keep the fastest.  The batch is applied repeatedly: the items' outputs
         (and inputs, for items applied in place) are overwritten.  Returns
-        {shape: ms} with the default shape under the key None."""
+        {shape: ms} with the default shape under the key None.  With cache, a batch
+        whose signature() was tuned before in this process takes that shape without
+        timing (and returns {}); results do not depend on the shape (bitwise)."""
+        key = self.signature() if cache and candidates is None else None
+        if key is not None and key in Batch._tuned:
+            self._set_tuning(Batch._tuned[key])
+            return {}
         stream = torch.cuda.current_stream(self.device)
         times = {}
         for t in [None] + list(candidates if candidates is not None else self.CANDIDATES):
@@ -171,5 +189,8 @@ class Batch:
             b.record(stream)
             b.synchronize()
             times[t] = a.elapsed_time(b) / reps
-        self._set_tuning(min(times, key=times.get))
+        best = min(times, key=times.get)
+        self._set_tuning(best)
+        if key is not None:
+            Batch._tuned[key] = best
         return times

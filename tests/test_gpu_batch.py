@@ -155,3 +155,21 @@ def test_batch_autotune(batch_setup):
     ref = _run_batch(ops, xs, False)
     for k, (a, e) in enumerate(zip(outs2, ref)):
         assert torch.equal(a, e), f"item {k}"
+
+
+def test_batch_autotune_cache(batch_setup):
+    """A second batch of the same item shapes on the same device takes the cached shape
+    without timing; a batch of other shapes is timed."""
+    ws, ops, xs = batch_setup
+    Batch._tuned.clear()
+    items, _ = _batch_items(ops, xs)
+    b = Batch(items)
+    times = b.autotune(reps=1)
+    assert times and b.signature() in Batch._tuned
+    items2, _ = _batch_items(ops, xs)
+    b2 = Batch(items2)
+    assert b2.autotune(reps=1) == {} and b2.tuning == b.tuning
+    items3, _ = _batch_items(ops[:2], xs[:2])
+    b3 = Batch(items3)
+    assert b3.signature() != b.signature()
+    assert b3.autotune(reps=1) != {}

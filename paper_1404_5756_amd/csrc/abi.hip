@@ -80,26 +80,40 @@ bool rf::force_sequential()
 }
 
 // One direction of the 3rd-RF in FP32 (forward when adj is false).  The tiled
-// kernels need one 2-D mask and 2-D sigma for all levels; other cases run the
+// kernels take one 2-D mask and sigma for all levels, or per-level tables when
+// either depends on depth (along x not with periodic rows); other cases run the
 // line-sequential kernels.
 static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void *coef, int dir,
                               bool adj, const float *in, float *out, int nlev, int nfields,
                               hipStream_t st)
 {
-    const bool tiled2d = g->mask_nlev == 1 && g->sigma_nlev == 1 && !force_sequential();
+    const bool depth = g->mask_nlev > 1 || g->sigma_nlev > 1;
+    const bool tiled = !force_sequential() && !(depth && dir == 0 && (g->flags & RF_PERIODIC_X));
     const int nplanes = nlev * nfields;
-    if (tiled2d && dir == 0 && h.lx) {
+    const long plane = (long)g->nx * g->ny;
+    LevTabs lt{};
+    lt.nlev = nlev;
+    lt.t = g->sigma_nlev > 1 ? plane : 0;
+    lt.lm = g->mask_nlev > 1 ? (dir == 0 ? (long)g->ny * kLaneMasks * lmx_stride(h.lx)
+                                         : (long)((g->nx + kYCols - 1) / kYCols) * kLaneMasks * lmy_stride(h.ly))
+                             : 0;
+    lt.phi = depth ? (dir == 0 ? phix_level_floats(g->ny) : phiy_level_floats(g->nx)) : 0;
+    lt.ky = depth ? ky_level_floats(g->nx, g->ny) : 0;
+    lt.end = h.end_nlev > 1 ? plane * 36 : 0;
+    const LevTabs *lv = depth ? &lt : nullptr;
+    if (tiled && dir == 0 && h.lx) {
         const float *pert = h.off_perx ? tab<float>(coef, h.off_perx) : nullptr;
         const float *endt = h.off_endf[0] ? tab<float>(coef, h.off_endf[0]) : nullptr;
         hipError_t e = fast_rf3_x(in, out, tab<float4>(coef, h.off_f32[0]), tab<uint64_t>(coef, h.off_lmx),
-                                  tab<float>(coef, h.off_phix), h.lx, g->nx, g->ny, nplanes, adj, pert, endt, st);
+                                  tab<float>(coef, h.off_phix), h.lx, g->nx, g->ny, nplanes, adj, pert, endt, lv,
+                                  st);
         if (e != hipErrorNotSupported) return e;
     }
-    if (tiled2d && dir == 1 && h.ly) {
+    if (tiled && dir == 1 && h.ly) {
         const float *endt = h.off_endf[1] ? tab<float>(coef, h.off_endf[1]) : nullptr;
         hipError_t e = fast_rf3_y(in, out, tab<float4>(coef, h.off_f32[1]), tab<float>(coef, h.off_ky),
                                   tab<uint64_t>(coef, h.off_lmy), tab<float>(coef, h.off_phiy), h.ly, g->nx, g->ny,
-                                  nplanes, adj, endt, st);
+                                  nplanes, adj, endt, lv, st);
         if (e != hipErrorNotSupported) return e;
     }
     const LineGeom G = geom(g, dir, nlev, nfields, coef);

@@ -484,13 +484,13 @@ BlockHeader layout(const rf_grid *g)
     if (h.lx) off = align256(off + (size_t)g->mask_nlev * g->ny * lmx_stride(h.lx) * kLaneMasks * 8);
     h.off_lmy = off;
     if (h.ly) off = align256(off + (size_t)g->mask_nlev * ((g->nx + kYCols - 1) / kYCols) * lmy_stride(h.ly) * kLaneMasks * 8);
+    const size_t clev = (size_t)coef_levels(g);
     h.off_phiy = off;
-    if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1)
-        off = align256(off + (size_t)((g->nx + kYCols - 1) / kYCols) * 4 * kYWaves * kYCols * 12 * 4);
+    if (h.ly) off = align256(off + clev * phiy_level_floats(g->nx) * 4);
     h.off_phix = off;
-    if (h.lx && g->mask_nlev == 1 && g->sigma_nlev == 1) off = align256(off + (size_t)g->ny * 4 * 64 * 12 * 4);
+    if (h.lx) off = align256(off + clev * phix_level_floats(g->ny) * 4);
     h.off_ky = off;
-    if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1) off = align256(off + (size_t)4 * plane * 3 * 4);
+    if (h.ly) off = align256(off + clev * ky_level_floats(g->nx, g->ny) * 4);
     const bool tiled2d = g->mask_nlev == 1 && g->sigma_nlev == 1;
     h.off_perx = h.off_perseq = 0;
     if (g->flags & RF_PERIODIC_X) {
@@ -555,17 +555,21 @@ extern "C" int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *si
                                                                 g->mask_nlev, h.ly);
         if (hipGetLastError() != hipSuccess) return RF_E_HIP;
     }
-    if (h.lx && g->mask_nlev == 1 && g->sigma_nlev == 1) {
-        if (setup_phi_x((const float4 *)(blk + h.off_f32[0]), (const uint8_t *)(blk + h.off_code[0]),
-                        (float *)(blk + h.off_phix), g->nx, g->ny, h.lx, st) != hipSuccess)
+    // scan tables per coefficient level, from that level's coefficients and codes
+    const size_t plane = (size_t)g->nx * g->ny;
+    for (int l = 0; l < coef_levels(g); ++l) {
+        const size_t ls = g->sigma_nlev > 1 ? l * plane : 0, lm = g->mask_nlev > 1 ? l * plane : 0;
+        if (h.lx && setup_phi_x((const float4 *)(blk + h.off_f32[0]) + ls, (const uint8_t *)(blk + h.off_code[0]) + lm,
+                                (float *)(blk + h.off_phix) + l * phix_level_floats(g->ny), g->nx, g->ny, h.lx,
+                                st) != hipSuccess)
             return RF_E_HIP;
-    }
-    if (h.ly && g->mask_nlev == 1 && g->sigma_nlev == 1) {
-        if (setup_phi_y((const float4 *)(blk + h.off_f32[1]), (const uint8_t *)(blk + h.off_code[1]),
-                        (float *)(blk + h.off_phiy), g->nx, g->ny, h.ly, st) != hipSuccess)
+        if (h.ly && setup_phi_y((const float4 *)(blk + h.off_f32[1]) + ls, (const uint8_t *)(blk + h.off_code[1]) + lm,
+                                (float *)(blk + h.off_phiy) + l * phiy_level_floats(g->nx), g->nx, g->ny, h.ly,
+                                st) != hipSuccess)
             return RF_E_HIP;
-        if (setup_ky_y((const float4 *)(blk + h.off_f32[1]), (const uint8_t *)(blk + h.off_code[1]),
-                       (float *)(blk + h.off_ky), g->nx, g->ny, h.ly, st) != hipSuccess)
+        if (h.ly && setup_ky_y((const float4 *)(blk + h.off_f32[1]) + ls, (const uint8_t *)(blk + h.off_code[1]) + lm,
+                               (float *)(blk + h.off_ky) + l * ky_level_floats(g->nx, g->ny), g->nx, g->ny, h.ly,
+                               st) != hipSuccess)
             return RF_E_HIP;
     }
     if (h.off_perx) {

@@ -10,7 +10,7 @@
 namespace rf {
 
 constexpr uint32_t kMagic = 0x52463321u;   // "RF3!"
-constexpr uint32_t kVersion = 4;
+constexpr uint32_t kVersion = 5;
 constexpr size_t kHeaderBytes = 512;         // the tables start here
 
 // Per-point coast code bits (one byte per point and direction).
@@ -53,9 +53,10 @@ struct BlockHeader {
     int32_t lx, ly;           // points per lane along x (64 lanes per row), per wave along y (16 waves)
     uint64_t off_lmx;         // uint64 [mask_nlev][ny][kLaneMasks][lxp]: FRESET, BRESET, not-SEA, end; bit c = chunk c
     uint64_t off_lmy;         // uint64 [mask_nlev][nblk][kLaneMasks][lys]: bit j = column 64*blk + j, entry 8+r = row r
-    uint64_t off_phiy;        // float [nblk][4][16][64][12]: y-chunk transfer matrices (2-D mask and sigma only)
-    uint64_t off_phix;        // float [ny][4][64][12]: x-chunk transfer matrices (2-D mask and sigma only)
-    uint64_t off_ky;          // float [4][ny][nx][3]: y local-pass K vectors (2-D mask and sigma only)
+    // per coefficient level (coef_levels: one, or nlev when the mask or sigma depends on depth):
+    uint64_t off_phiy;        // float [clev][nblk][4][16][64][12]: y-chunk transfer matrices
+    uint64_t off_phix;        // float [clev][ny][4][64][12]: x-chunk transfer matrices
+    uint64_t off_ky;          // float [clev][4][ny][nx][3]: y local-pass K vectors
     // RF_PERIODIC_X (0 otherwise):
     uint64_t off_perx;        // float [ny][4][kPerXEntries][12]: cyclic scan of the tiled x kernel (2-D only)
     uint64_t off_perseq;      // double [sigma_nlev][ny][kPerSeq]: one-lap fixed points of the sequential kernels
@@ -116,6 +117,25 @@ __host__ __device__ inline int tile_ly(int ny)
     return 0;
 }
 __host__ __device__ constexpr int y_planes_per_lane(int ly) { return ly <= 45 ? 2 : 1; }
+
+// levels of the tiled kernels' scan tables: the scan matrices of a line follow from
+// its coefficients and its coast codes, so they depend on depth when either does
+inline int coef_levels(const rf_grid *g) { return g->mask_nlev > g->sigma_nlev ? g->mask_nlev : g->sigma_nlev; }
+inline long phix_level_floats(int ny) { return (long)ny * 4 * 64 * 12; }
+inline long phiy_level_floats(int nx) { return (long)((nx + kYCols - 1) / kYCols) * 4 * kYWaves * kYCols * 12; }
+inline long ky_level_floats(int nx, int ny) { return 4L * nx * ny * 3; }
+
+// Depth-dependent tables of the tiled kernels: plane p of [nfields][nlev] has
+// level p % nlev, and each table of that level starts this many elements after
+// level 0's (0: one table serves every level).
+struct LevTabs {
+    int nlev;
+    long t;      // float4 coefficients (sigma level)
+    long lm;     // uint64 lane masks (mask level)
+    long phi;    // float chunk transfer matrices (coefficient level)
+    long ky;     // float y K vectors (coefficient level; y only)
+    long end;    // float exact-end maps (coefficient level)
+};
 
 // Batched FP32 application (batch.hip builds these on the host).  One entry per
 // item with its buffers and the tables of both directions; one unit per

@@ -570,6 +570,118 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
                              stage[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)], PERT, ENDT);
 }
 
+// Depth-dependent tables (LevTabs): each level has its own coefficients, lane
+// masks and scan matrices, so every wave takes one (level, row) on its own (that
+// row's line in each field) and builds its scan matrices itself, one sweep at a
+// time, in its own LDS slice.  A wave reads and writes only its own slices, so
+// the kernel has no workgroup barrier and a wave past the last row returns.
+template <int L, bool ADJ, bool END>
+__global__ __launch_bounds__(64 * kXWaves, 2) void k_rf3x_lev(const float *in, float *out,
+                                                             const float4 *__restrict__ T,
+                                                             const uint64_t *__restrict__ LM,
+                                                             const float *__restrict__ PHI, int nx, int ny,
+                                                             int nfields, LevTabs S, const float *__restrict__ ENDT)
+{
+    __shared__ float K[kXWaves][64 * kKs];
+    __shared__ __align__(16) float stage[kXWaves][x_stage_floats<L>()];
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long u = (long)blockIdx.x * kXWaves + wave;   // level * ny + row
+    if (u >= (long)S.nlev * ny) return;
+    const int lev = (int)(u / ny), row = (int)(u % ny);
+    T += lev * S.t;
+    LM += lev * S.lm;
+    PHI += lev * S.phi;
+    float *Kw = K[wave], *stg = stage[wave];
+    const long plane = (long)nx * ny;
+    const int x0 = lane * L;
+    const uint32_t line_bytes = (uint32_t)nx * 4u;
+
+    XRow<L, ADJ> R;
+    {
+        const Rsrc tr = make_rsrc(T + (long)row * nx, (uint32_t)nx * 16u);
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(tr, (x0 + i) * 16, 0, 0);
+            R.kb[i] = __uint_as_float(c.x);
+            R.kg[i] = __uint_as_float(c.y);
+            R.k2[i] = __uint_as_float(c.z);
+            R.k3[i] = __uint_as_float(c.w);
+        }
+    }
+    R.lm = as_const(LM + (long)row * kLaneMasks * XRow<L, ADJ>::LP);
+    const float *pa = PHI + (((long)row * 4 + (ADJ ? 2 : 0)) * 64 + lane) * 12;   // ascending; descending next
+    const int nst = (nx + 255) / 256;
+    constexpr int NR = (L + 3) / 4;
+    for (int f = 0; f < nfields; ++f) {
+        const long ln = (long)f * S.nlev + lev;
+        {
+            const Rsrc r = make_rsrc(in + ln * plane + (long)row * nx, line_bytes);
+            u32x4 q[NR];
+#pragma unroll
+            for (int it = 0; it < NR; ++it)
+                q[it] = __builtin_amdgcn_raw_buffer_load_b128(r, (4 * lane + 256 * it) * 4, 0, kStreamLoadX);
+#pragma unroll
+            for (int it = 0; it < NR; ++it) *reinterpret_cast<u32x4 *>(stg + 4 * lane + 256 * it) = q[it];
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS writes done
+        __builtin_amdgcn_wave_barrier();
+        float v[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) v[i] = stg[x0 + i];
+        {
+            mask_ptr sp = R.lm + 2 * XRow<L, ADJ>::LP + fresh_int(0);
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                v[i] = zero_if(v[i], sp[i]);   // input only at sea points
+                if (!ADJ) v[i] = R.kb[i] * v[i];
+            }
+        }
+        float A[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) A[e] = pa[e];
+        ks_build<false>(A, Kw, lane);
+        St x{0.f, 0.f, 0.f};
+        R.template asc<1>(x, v);
+        x = ks_carry<false>(x, Kw, lane);
+        if (!END) {
+            R.template asc<2>(x, v);
+        } else {
+            float co1 = 0.f, co2 = 0.f;
+            R.asc2_end(x, v, ENDT + lev * S.end + (long)row * nx * 36 + (ADJ ? 12 : 0), lane, co1, co2);
+            const float b1 = dpp<DPP_WAVE_SHL1, 0xF>(co1), b2 = dpp<DPP_WAVE_SHL1, 0xF>(co2);
+            v[L - 1] += b1;
+            if (L >= 2) v[L >= 2 ? L - 2 : 0] += b2;
+            else v[L - 1] += dpp<DPP_WAVE_SHL1, 0xF>(b2);
+        }
+#pragma unroll
+        for (int e = 0; e < 9; ++e) A[e] = pa[64 * 12 + e];
+        ks_build<true>(A, Kw, lane);
+        St y{0.f, 0.f, 0.f};
+        R.template desc<1>(y, v);
+        y = ks_carry<true>(y, Kw, lane);
+        R.template desc<2>(y, v);
+#pragma unroll
+        for (int i = 0; i < L; ++i) stg[x0 + i] = v[i];
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        const Rsrc ro = make_rsrc(out + ln * plane + (long)row * nx, line_bytes);
+#pragma unroll
+        for (int it = 0; it < NR; ++it) {
+            if (it < nst) {
+                const f4 q = *reinterpret_cast<const f4 *>(stg + 4 * lane + 256 * it);
+                u32x4 w;
+                w.x = __float_as_uint(q.x);
+                w.y = __float_as_uint(q.y);
+                w.z = __float_as_uint(q.z);
+                w.w = __float_as_uint(q.w);
+                __builtin_amdgcn_raw_buffer_store_b128(w, ro, (4 * lane + 256 * it) * 4, 0, kStreamStoreX);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // the staging reads are done before the next line's writes
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // Batched form: one workgroup per work unit {item, row, group, groups}; the
 // second pass of a V_H application reads the first pass's output (src_out).
 // One launch serves every tile size of an occupancy class (x_batch_class):
@@ -929,6 +1041,40 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float
     y_planes<L, ADJ, END>(in, out, T, KY, LM, PHI, nx, ny, blk, pa, pb, (j + 2) % 3, phi, bsh, ENDT, xch);
 }
 
+// Depth-dependent tables (LevTabs): planes [pa, pb) of one column block one at a
+// time (plane p has level p % nlev), each with its level's tables; the level's
+// chunk transfer matrices go into LDS before each plane.
+template <int L, bool ADJ, bool END>
+__global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_lev(const float *in, float *out, const float4 *T,
+                                                             const float *KY, const uint64_t *__restrict__ LM,
+                                                             const float *__restrict__ PHI, int nx, int ny,
+                                                             int nplanes, int nblk, int nslot, LevTabs S,
+                                                             const float *__restrict__ ENDT)
+{
+    __shared__ float phi[2][kYWaves][kYCols * 9];
+    __shared__ float bsh[2 * kYWaves * 2 * kYCols * 3];
+    __shared__ float xch[END ? kYWaves * 2 * 2 * kYCols : 1];
+    const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
+    const int blk = (slot / nslot) * 8 + xcd, j = slot % nslot;
+    if (blk >= nblk) return;
+    const int pa = (int)((long)j * nplanes / nslot), pb = (int)((long)(j + 1) * nplanes / nslot);
+    const int k0 = ADJ ? 2 : 0;
+    for (int p = pa; p < pb; ++p) {
+        const int lev = p % S.nlev;
+        const float *ph = PHI + lev * S.phi;
+        for (int e = threadIdx.x; e < 2 * kYWaves * kYCols; e += 64 * kYWaves) {
+            const int sw = e / (kYWaves * kYCols), rest = e % (kYWaves * kYCols);
+            const float *src = ph + (((long)blk * 4 + k0 + sw) * kYWaves * kYCols + rest) * 12;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) phi[sw][rest / kYCols][(rest % kYCols) * 9 + q] = src[q];
+        }
+        __syncthreads();
+        y_unit<L, ADJ, 1, END>(in, out, T + lev * S.t, KY + lev * S.ky, LM + lev * S.lm, nx, ny, blk, p, phi, bsh,
+                               END ? ENDT + lev * S.end : nullptr, xch);
+        __syncthreads();   // phi, bsh and xch are rewritten for the next plane
+    }
+}
+
 // Batched form: one workgroup per work unit {item, column block, first and end
 // plane}.  The tile size follows from the item's ny, so one launch serves the
 // units of every tile size (the work list puts the largest tiles first and the
@@ -1219,8 +1365,20 @@ int x_groups(int ny, int nplanes, int gmax)
 
 template <int L, bool ADJ>
 static hipError_t launch_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI,
-                           int nx, int ny, int nplanes, const float *PERT, const float *ENDT, hipStream_t st)
+                           int nx, int ny, int nplanes, const float *PERT, const float *ENDT, const LevTabs *lv,
+                           hipStream_t st)
 {
+    if (lv) {   // depth-dependent tables: one wave per (level, row)
+        if (PERT || lv->nlev < 1 || nplanes % lv->nlev) return hipErrorNotSupported;
+        const unsigned nb = (unsigned)(((long)lv->nlev * ny + kXWaves - 1) / kXWaves);
+        if (ENDT)
+            k_rf3x_lev<L, ADJ, true><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes / lv->nlev, *lv,
+                                                                  ENDT);
+        else
+            k_rf3x_lev<L, ADJ, false><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes / lv->nlev,
+                                                                   *lv, nullptr);
+        return hipGetLastError();
+    }
     const int groups = x_groups(ny, nplanes, 8);
     const unsigned nb = (unsigned)(((ny + 7) / 8) * 8 * groups);
     if (PERT && ENDT) return hipErrorNotSupported;   // periodic rows with exact ends: sequential kernels
@@ -1249,10 +1407,12 @@ static double y_range_cost(int n, int pm)
 
 template <int L, bool ADJ>
 static hipError_t launch_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
-                           const float *PHI, int nx, int ny, int nplanes, const float *ENDT, hipStream_t st)
+                           const float *PHI, int nx, int ny, int nplanes, const float *ENDT, const LevTabs *lv,
+                           hipStream_t st)
 {
-    constexpr int PM = y_planes_per_lane(L);
-    static_assert(PM == 1 || PM == 2, "planes per lane");
+    static_assert(y_planes_per_lane(L) == 1 || y_planes_per_lane(L) == 2, "planes per lane");
+    // depth-dependent tables: one plane per unit
+    const int PM = lv ? 1 : y_planes_per_lane(L);
     const int nblk = (nx + kYCols - 1) / kYCols;
     // slots (workgroups) per column block: one workgroup per CU at a time, so
     // minimise (rounds of workgroups) x (cost of the largest plane range)
@@ -1265,6 +1425,16 @@ static hipError_t launch_y(const float *in, float *out, const float4 *T, const f
         if (best_cost < 0 || cost < best_cost - 1e-9) { best_cost = cost; best = sl; }
     }
     const unsigned nb = (unsigned)(nb8 * best);
+    if (lv) {
+        if (lv->nlev < 1) return hipErrorNotSupported;
+        if (ENDT)
+            k_rf3y_lev<L, ADJ, true><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nplanes, nblk, best,
+                                                                  *lv, ENDT);
+        else
+            k_rf3y_lev<L, ADJ, false><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nplanes, nblk,
+                                                                   best, *lv, nullptr);
+        return hipGetLastError();
+    }
     if (ENDT)
         k_rf3y<L, ADJ, true><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nplanes, nblk, best, ENDT);
     else
@@ -1275,15 +1445,16 @@ static hipError_t launch_y(const float *in, float *out, const float4 *T, const f
 
 #define RF_X_CASE(Lv)                                                                                     \
     case Lv:                                                                                              \
-        return adj ? launch_x<Lv, true>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, ENDT, st)             \
-                   : launch_x<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, ENDT, st);
+        return adj ? launch_x<Lv, true>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, ENDT, lv, st)         \
+                   : launch_x<Lv, false>(in, out, T, LM, PHI, nx, ny, nplanes, PERT, ENDT, lv, st);
 #define RF_Y_CASE(Lv)                                                                                     \
     case Lv:                                                                                              \
-        return adj ? launch_y<Lv, true>(in, out, T, KY, LM, PHI, nx, ny, nplanes, ENDT, st)               \
-                   : launch_y<Lv, false>(in, out, T, KY, LM, PHI, nx, ny, nplanes, ENDT, st);
+        return adj ? launch_y<Lv, true>(in, out, T, KY, LM, PHI, nx, ny, nplanes, ENDT, lv, st)           \
+                   : launch_y<Lv, false>(in, out, T, KY, LM, PHI, nx, ny, nplanes, ENDT, lv, st);
 
 hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int lx,
-                      int nx, int ny, int nplanes, bool adj, const float *PERT, const float *ENDT, hipStream_t st)
+                      int nx, int ny, int nplanes, bool adj, const float *PERT, const float *ENDT, const LevTabs *lv,
+                      hipStream_t st)
 {
     switch (lx) {
         RF_X_CASE(1) RF_X_CASE(3) RF_X_CASE(5) RF_X_CASE(7) RF_X_CASE(9) RF_X_CASE(11) RF_X_CASE(13)
@@ -1295,7 +1466,7 @@ hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64
 
 hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
                       const float *PHI, int ly, int nx, int ny, int nplanes, bool adj, const float *ENDT,
-                      hipStream_t st)
+                      const LevTabs *lv, hipStream_t st)
 {
     // scalar row offsets into the coefficient table are 32-bit
     if ((long)nx * ny * 16 >= (1L << 31)) return hipErrorNotSupported;

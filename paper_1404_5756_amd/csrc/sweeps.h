@@ -27,12 +27,14 @@ hipError_t seq_rf1_f64(const double *in, double *out, const double2 *C, const ui
 
 namespace rf {
 // tiled FP32 kernels (sweep_fast.hip); hipErrorNotSupported when the tile size is not covered
-// PERT: cyclic-scan tables of periodic rows, ENDT: exact-end tables (rf3_internal.h), or null
+// PERT: cyclic-scan tables of periodic rows, ENDT: exact-end tables (rf3_internal.h), or null;
+// lv: per-level strides of depth-dependent tables (null: one table for every plane)
 hipError_t fast_rf3_x(const float *in, float *out, const float4 *T, const uint64_t *LM, const float *PHI, int lx,
-                      int nx, int ny, int nplanes, bool adj, const float *PERT, const float *ENDT, hipStream_t st);
+                      int nx, int ny, int nplanes, bool adj, const float *PERT, const float *ENDT, const LevTabs *lv,
+                      hipStream_t st);
 hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float *KY, const uint64_t *LM,
                       const float *PHI, int ly, int nx, int ny, int nplanes, bool adj, const float *ENDT,
-                      hipStream_t st);
+                      const LevTabs *lv, hipStream_t st);
 // batched forms over a work list: x units of one launch share the occupancy
 // class of their tile size (x_batch_class), a y launch takes units of any tile
 // size; each unit's tile size follows from its item's nx or ny

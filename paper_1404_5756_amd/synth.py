@@ -116,6 +116,22 @@ def c3_anisotropic(nlev=50):
                     seed=w.seed)
 
 
+def c3_depth(nlev=50):
+    """The C3 grid with a depth-dependent mask and length scales (Sec. 5: the global
+    configuration's land grows with depth and its length scales depend on depth): level k
+    thresholds C3's smoothed blob field at the land fraction 0.30 + 0.25 k/(nlev-1), so land
+    only grows downwards, and sigma shrinks with depth, times (1 - 0.3 k/(nlev-1))."""
+    seed = SEEDS["c3"]
+    nx, ny = 1440, 720
+    z = gaussian_filter(_rng(seed, 0).standard_normal((ny, nx)), 10.0, mode="wrap")
+    fr = 0.30 + 0.25 * np.arange(nlev) / max(nlev - 1, 1)
+    mask = np.stack([(z > np.quantile(z, f)).astype(np.uint8) for f in fr])
+    lat = np.deg2rad(-90.0 + (np.arange(ny) + 0.5) * 0.25)
+    s2 = np.repeat((1.5 + 10.5 * np.cos(lat) ** 2)[:, None], nx, axis=1)
+    sig = np.stack([s2 * (1.0 - 0.3 * k / max(nlev - 1, 1)) for k in range(nlev)])
+    return Workload("c3_depth_1440x720x50", nx, ny, nlev, 1, mask, sig, sig.copy(), seed=seed)
+
+
 def c4_batch(nitems=64):
     """64 grids with nx~U[128,1024], ny~U[128,768], nlev~U[1,75], land~U[0.1,0.5], sigma in [2, 8]."""
     seed = SEEDS["c4"]

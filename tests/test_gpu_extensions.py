@@ -138,7 +138,7 @@ TOL64_END = 1e-11
 
 ECASES = [
     # seed, ny, nx, nlev, 3-D mask, periodic: tiles x 23 / y 45 (two planes per lane), x 33 / y 56 (one
-    # plane), x 1 / y 1 (one point per lane, one row per wave), a per-level mask (sequential FP32), and
+    # plane), x 1 / y 1 (one point per lane, one row per wave), a per-level mask (per-level tables), and
     # periodic rows with exact ends (sequential FP32)
     (51, 720, 1440, 3, False, False),
     (52, 801, 2112, 1, False, False),

@@ -56,13 +56,14 @@ def test_c3_forward_and_adjoint_full(orc):
     assert ef < TOL32 and ea < TOL32
 
 
-@pytest.mark.parametrize("variant", ["anisotropic", "periodic_x", "exact_ends"])
+@pytest.mark.parametrize("variant", ["anisotropic", "periodic_x", "exact_ends", "depth"])
 def test_c3_variants_full(orc, variant):
     """C3 with anisotropic, inhomogeneous length scales (zonal twice meridional at the equator),
-    with zonally periodic rows, and with exact end conditions: forward and adjoint at every point,
-    field-wide and line by line (exact ends: its stated per-line bound)."""
+    with zonally periodic rows, with exact end conditions, and with a depth-dependent mask and
+    sigma (one plane per level: the line-sequential FP32 kernels): forward and adjoint at every
+    point, field-wide and line by line (exact ends: its stated per-line bound)."""
     dev = torch.device("cuda:0")
-    w = synth.c3_anisotropic() if variant == "anisotropic" else synth.c3_global()
+    w = {"anisotropic": synth.c3_anisotropic, "depth": synth.c3_depth}.get(variant, synth.c3_global)()
     kw = {"periodic_x": variant == "periodic_x", "exact_ends": variant == "exact_ends"}
     flags = (orc.PERIODIC_X if kw["periodic_x"] else 0) | (orc.EXACT_ENDS if kw["exact_ends"] else 0)
     xh = w.field(np.float32)

@@ -81,14 +81,14 @@ bool rf::force_sequential()
 
 // One direction of the 3rd-RF in FP32 (forward when adj is false).  The tiled
 // kernels take one 2-D mask and sigma for all levels, or per-level tables when
-// either depends on depth (along x not with periodic rows); other cases run the
-// line-sequential kernels.
+// either depends on depth; other cases (tile sizes not covered, periodic rows with
+// exact ends along x) run the line-sequential kernels.
 static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void *coef, int dir,
                               bool adj, const float *in, float *out, int nlev, int nfields,
                               hipStream_t st)
 {
     const bool depth = g->mask_nlev > 1 || g->sigma_nlev > 1;
-    const bool tiled = !force_sequential() && !(depth && dir == 0 && (g->flags & RF_PERIODIC_X));
+    const bool tiled = !force_sequential();
     const int nplanes = nlev * nfields;
     const long plane = (long)g->nx * g->ny;
     LevTabs lt{};
@@ -100,6 +100,7 @@ static hipError_t rf3_dir_f32(const rf_grid *g, const BlockHeader &h, const void
     lt.phi = depth ? (dir == 0 ? phix_level_floats(g->ny) : phiy_level_floats(g->nx)) : 0;
     lt.ky = depth ? ky_level_floats(g->nx, g->ny) : 0;
     lt.end = h.end_nlev > 1 ? plane * 36 : 0;
+    lt.per = depth ? perx_level_floats(g->ny) : 0;
     const LevTabs *lv = depth ? &lt : nullptr;
     if (tiled && dir == 0 && h.lx) {
         const float *pert = h.off_perx ? tab<float>(coef, h.off_perx) : nullptr;

@@ -491,10 +491,9 @@ BlockHeader layout(const rf_grid *g)
     if (h.lx) off = align256(off + clev * phix_level_floats(g->ny) * 4);
     h.off_ky = off;
     if (h.ly) off = align256(off + clev * ky_level_floats(g->nx, g->ny) * 4);
-    const bool tiled2d = g->mask_nlev == 1 && g->sigma_nlev == 1;
     h.off_perx = h.off_perseq = 0;
     if (g->flags & RF_PERIODIC_X) {
-        if (h.lx && tiled2d) { h.off_perx = off; off = align256(off + (size_t)g->ny * 4 * kPerXEntries * 12 * 4); }
+        if (h.lx) { h.off_perx = off; off = align256(off + clev * perx_level_floats(g->ny) * 4); }
         h.off_perseq = off;
         off = align256(off + (size_t)g->sigma_nlev * g->ny * kPerSeq * 8);
     }
@@ -572,9 +571,11 @@ extern "C" int rf_coeffs(const rf_grid *g, const uint8_t *mask, const double *si
                                st) != hipSuccess)
             return RF_E_HIP;
     }
-    if (h.off_perx) {
-        if (setup_per_x((const float4 *)(blk + h.off_f32[0]), (const uint8_t *)(blk + h.off_code[0]),
-                        (float *)(blk + h.off_perx), g->nx, g->ny, h.lx, st) != hipSuccess)
+    for (int l = 0; h.off_perx && l < coef_levels(g); ++l) {
+        const size_t ls = g->sigma_nlev > 1 ? l * plane : 0, lm = g->mask_nlev > 1 ? l * plane : 0;
+        if (setup_per_x((const float4 *)(blk + h.off_f32[0]) + ls, (const uint8_t *)(blk + h.off_code[0]) + lm,
+                        (float *)(blk + h.off_perx) + l * perx_level_floats(g->ny), g->nx, g->ny, h.lx,
+                        st) != hipSuccess)
             return RF_E_HIP;
     }
     if (h.end_nlev) {

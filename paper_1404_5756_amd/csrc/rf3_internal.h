@@ -58,7 +58,7 @@ struct BlockHeader {
     uint64_t off_phix;        // float [clev][ny][4][64][12]: x-chunk transfer matrices
     uint64_t off_ky;          // float [clev][4][ny][nx][3]: y local-pass K vectors
     // RF_PERIODIC_X (0 otherwise):
-    uint64_t off_perx;        // float [ny][4][kPerXEntries][12]: cyclic scan of the tiled x kernel (2-D only)
+    uint64_t off_perx;        // float [clev][ny][4][kPerXEntries][12]: cyclic scan of the tiled x kernel
     uint64_t off_perseq;      // double [sigma_nlev][ny][kPerSeq]: one-lap fixed points of the sequential kernels
     // RF_EXACT_ENDS (0 otherwise): 3x3 end matrices at segment ends, zero elsewhere
     uint64_t off_endd[2];     // double [end_nlev][ny][nx][2][9]: forward J M, adjoint M^T J^T (on p and z)
@@ -124,6 +124,7 @@ inline int coef_levels(const rf_grid *g) { return g->mask_nlev > g->sigma_nlev ?
 inline long phix_level_floats(int ny) { return (long)ny * 4 * 64 * 12; }
 inline long phiy_level_floats(int nx) { return (long)((nx + kYCols - 1) / kYCols) * 4 * kYWaves * kYCols * 12; }
 inline long ky_level_floats(int nx, int ny) { return 4L * nx * ny * 3; }
+inline long perx_level_floats(int ny) { return (long)ny * 4 * kPerXEntries * 12; }
 
 // Depth-dependent tables of the tiled kernels: plane p of [nfields][nlev] has
 // level p % nlev, and each table of that level starts this many elements after
@@ -135,6 +136,7 @@ struct LevTabs {
     long phi;    // float chunk transfer matrices (coefficient level)
     long ky;     // float y K vectors (coefficient level; y only)
     long end;    // float exact-end maps (coefficient level)
+    long per;    // float cyclic-scan tables of periodic rows (coefficient level; x only)
 };
 
 // Batched FP32 application (batch.hip builds these on the host).  One entry per

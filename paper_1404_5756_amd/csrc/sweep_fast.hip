@@ -571,17 +571,20 @@ __global__ __launch_bounds__(64 * kXWaves, (L <= 23 ? 3 : 2)) void k_rf3x(
 }
 
 // Depth-dependent tables (LevTabs): each level has its own coefficients, lane
-// masks and scan matrices, so every wave takes one (level, row) on its own (that
-// row's line in each field) and builds its scan matrices itself, one sweep at a
-// time, in its own LDS slice.  A wave reads and writes only its own slices, so
-// the kernel has no workgroup barrier and a wave past the last row returns.
-template <int L, bool ADJ, bool END>
+// masks, scan matrices and (periodic rows) cyclic-scan tables, so every wave
+// takes one (level, row) on its own (that row's line in each field) and builds
+// its scan matrices itself, one sweep at a time, in its own LDS slice.  A wave
+// reads and writes only its own slices, so the kernel has no workgroup barrier
+// and a wave past the last row returns.
+template <int L, bool ADJ, bool PER, bool END>
 __global__ __launch_bounds__(64 * kXWaves, 2) void k_rf3x_lev(const float *in, float *out,
                                                              const float4 *__restrict__ T,
                                                              const uint64_t *__restrict__ LM,
                                                              const float *__restrict__ PHI, int nx, int ny,
-                                                             int nfields, LevTabs S, const float *__restrict__ ENDT)
+                                                             int nfields, LevTabs S, const float *__restrict__ PERT,
+                                                             const float *__restrict__ ENDT)
 {
+    static_assert(!(PER && END), "periodic rows with exact ends run the line-sequential kernels");
     __shared__ float K[kXWaves][64 * kKs];
     __shared__ __align__(16) float stage[kXWaves][x_stage_floats<L>()];
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -609,7 +612,7 @@ __global__ __launch_bounds__(64 * kXWaves, 2) void k_rf3x_lev(const float *in, f
         }
     }
     R.lm = as_const(LM + (long)row * kLaneMasks * XRow<L, ADJ>::LP);
-    const float *pa = PHI + (((long)row * 4 + (ADJ ? 2 : 0)) * 64 + lane) * 12;   // ascending; descending next
+    const float *ph = PHI + (((long)row * 4 + (ADJ ? 2 : 0)) * 64 + lane) * 12;   // ascending; descending next
     const int nst = (nx + 255) / 256;
     constexpr int NR = (L + 3) / 4;
     for (int f = 0; f < nfields; ++f) {
@@ -638,28 +641,70 @@ __global__ __launch_bounds__(64 * kXWaves, 2) void k_rf3x_lev(const float *in, f
         }
         float A[9];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) A[e] = pa[e];
+        for (int e = 0; e < 9; ++e) A[e] = ph[e];
         ks_build<false>(A, Kw, lane);
         St x{0.f, 0.f, 0.f};
-        R.template asc<1>(x, v);
-        x = ks_carry<false>(x, Kw, lane);
-        if (!END) {
-            R.template asc<2>(x, v);
-        } else {
-            float co1 = 0.f, co2 = 0.f;
-            R.asc2_end(x, v, ENDT + lev * S.end + (long)row * nx * 36 + (ADJ ? 12 : 0), lane, co1, co2);
-            const float b1 = dpp<DPP_WAVE_SHL1, 0xF>(co1), b2 = dpp<DPP_WAVE_SHL1, 0xF>(co2);
-            v[L - 1] += b1;
-            if (L >= 2) v[L >= 2 ? L - 2 : 0] += b2;
-            else v[L - 1] += dpp<DPP_WAVE_SHL1, 0xF>(b2);
-        }
+        if (!PER) {
+            R.template asc<1>(x, v);
+            x = ks_carry<false>(x, Kw, lane);
+            if (!END) {
+                R.template asc<2>(x, v);
+            } else {
+                float co1 = 0.f, co2 = 0.f;
+                R.asc2_end(x, v, ENDT + lev * S.end + (long)row * nx * 36 + (ADJ ? 12 : 0), lane, co1, co2);
+                const float b1 = dpp<DPP_WAVE_SHL1, 0xF>(co1), b2 = dpp<DPP_WAVE_SHL1, 0xF>(co2);
+                v[L - 1] += b1;
+                if (L >= 2) v[L >= 2 ? L - 2 : 0] += b2;
+                else v[L - 1] += dpp<DPP_WAVE_SHL1, 0xF>(b2);
+            }
 #pragma unroll
-        for (int e = 0; e < 9; ++e) A[e] = pa[64 * 12 + e];
-        ks_build<true>(A, Kw, lane);
-        St y{0.f, 0.f, 0.f};
-        R.template desc<1>(y, v);
-        y = ks_carry<true>(y, Kw, lane);
-        R.template desc<2>(y, v);
+            for (int e = 0; e < 9; ++e) A[e] = ph[64 * 12 + e];
+            ks_build<true>(A, Kw, lane);
+            St y{0.f, 0.f, 0.f};
+            R.template desc<1>(y, v);
+            y = ks_carry<true>(y, Kw, lane);
+            R.template desc<2>(y, v);
+        } else {
+            // periodic row: the cyclic carry scans of the 2-D kernel (x_rows), with
+            // this level's cyclic-scan tables
+            const int clast = (nx - 1) / L, slast = (nx - 1) % L;
+            const float *qa = PERT + lev * S.per + ((long)row * 4 + (ADJ ? 2 : 0)) * kPerXEntries * 12;
+            const float *qd = PERT + lev * S.per + ((long)row * 4 + (ADJ ? 3 : 1)) * kPerXEntries * 12;
+            St saved{0.f, 0.f, 0.f};
+            R.template asc<1, true>(x, v, slast, &saved);
+            x = ks_carry<false>(x, Kw, lane);
+            {
+                float M[9];
+                load_m3(qa + 65 * 12, M);
+                St bw = saved;
+                mat_acc(M, x, bw);
+                const St b{__int_as_float(__builtin_amdgcn_readlane(__float_as_int(bw.a), clast)),
+                           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bw.b), clast)),
+                           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bw.c), clast))};
+                load_m3(qa + 64 * 12, M);
+                St x0{0.f, 0.f, 0.f};
+                mat_acc(M, b, x0);
+                load_m3(qa + lane * 12, M);
+                mat_acc(M, x0, x);
+            }
+            R.template asc<2>(x, v);
+#pragma unroll
+            for (int e = 0; e < 9; ++e) A[e] = ph[64 * 12 + e];
+            ks_build<true>(A, Kw, lane);
+            St y{0.f, 0.f, 0.f};
+            R.template desc<1>(y, v);
+            St out0;
+            y = ks_carry<true>(y, Kw, lane, &out0);
+            St xw{0.f, 0.f, 0.f};
+            {
+                float M[9];
+                load_m3(qd + 64 * 12, M);
+                mat_acc(M, out0, xw);
+                load_m3(qd + lane * 12, M);
+                mat_acc(M, xw, y);
+            }
+            R.template desc<2, true>(y, v, slast, lane == clast, xw);
+        }
 #pragma unroll
         for (int i = 0; i < L; ++i) stg[x0 + i] = v[i];
         __builtin_amdgcn_s_waitcnt(0xc07f);
@@ -1369,14 +1414,18 @@ static hipError_t launch_x(const float *in, float *out, const float4 *T, const u
                            hipStream_t st)
 {
     if (lv) {   // depth-dependent tables: one wave per (level, row)
-        if (PERT || lv->nlev < 1 || nplanes % lv->nlev) return hipErrorNotSupported;
+        if ((PERT && ENDT) || lv->nlev < 1 || nplanes % lv->nlev) return hipErrorNotSupported;
         const unsigned nb = (unsigned)(((long)lv->nlev * ny + kXWaves - 1) / kXWaves);
-        if (ENDT)
-            k_rf3x_lev<L, ADJ, true><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes / lv->nlev, *lv,
-                                                                  ENDT);
+        const int nf = nplanes / lv->nlev;
+        if (PERT)
+            k_rf3x_lev<L, ADJ, true, false><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nf, *lv, PERT,
+                                                                         nullptr);
+        else if (ENDT)
+            k_rf3x_lev<L, ADJ, false, true><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nf, *lv,
+                                                                         nullptr, ENDT);
         else
-            k_rf3x_lev<L, ADJ, false><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nplanes / lv->nlev,
-                                                                   *lv, nullptr);
+            k_rf3x_lev<L, ADJ, false, false><<<nb, 64 * kXWaves, 0, st>>>(in, out, T, LM, PHI, nx, ny, nf, *lv,
+                                                                          nullptr, nullptr);
         return hipGetLastError();
     }
     const int groups = x_groups(ny, nplanes, 8);

@@ -5,8 +5,8 @@ oracle with the same flags.
 Periodic grids have all-sea rows (cyclic lines, solved by one fixed point per
 line), rows whose sea runs wrap from x = nx-1 to x = 0, and row lengths that
 fill the x tile exactly or leave padding in the last chunk.  Every path is
-checked: the tiled FP32 kernels (field-wide relative L2 1e-5 and line by line),
-the line-sequential FP32 kernels (RF3_SEQUENTIAL=1, and per-level masks), FP64
+checked: the tiled FP32 kernels (field-wide relative L2 1e-5 and line by line;
+2-D and per-level tables), the line-sequential FP32 kernels (RF3_SEQUENTIAL=1), FP64
 (1e-12), the 1st-RF (FP64), forward and adjoint, in place.
 """
 import os
@@ -41,12 +41,13 @@ def periodic_case(seed, ny, nx, nlev, mask_3d=False, sigma=(1.5, 12.0)):
 
 PCASES = [
     # seed, ny, nx, nlev, 3-D mask: x tiles of 23 (1440 = 64*22.5: padding), 23 (1472 = 64*23: none),
-    # 1 (nx = 50), 33 (2100), and a per-level mask (sequential FP32 path)
+    # 1 (nx = 50), 33 (2100), and per-level masks (per-level tables: x tiles of 5 and 23)
     (41, 40, 1440, 2, False),
     (42, 33, 1472, 2, False),
     (43, 30, 50, 3, False),
     (44, 21, 2100, 1, False),
     (45, 35, 300, 3, True),
+    (46, 48, 1440, 3, True),
 ]
 
 

@@ -150,7 +150,8 @@ def k_frontier(torch, dev, w, x, ms_rf3_fwd, args):
 def bench_variants(torch, dev, args):
     """C3 step (forward + adjoint) with the options beyond the paper's scheme: zonally periodic
     rows, exact end conditions, anisotropic inhomogeneous length scales, and a depth-dependent
-    mask and sigma (the line-sequential FP32 kernels) (same field)."""
+    mask and sigma (per-level tables) (same field); and C2 (T and S, 72 levels) with a
+    depth-dependent mask and sigma (its own two-field input)."""
     from paper_1404_5756_amd import synth
     from paper_1404_5756_amd.operator import HorizontalCovariance
     res = {}
@@ -160,7 +161,11 @@ def bench_variants(torch, dev, args):
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for name, w, kw in (("periodic_x", base, {"periodic_x": True}), ("exact_ends", base, {"exact_ends": True}),
-                        ("anisotropic", synth.c3_anisotropic(), {}), ("depth_mask_sigma", synth.c3_depth(), {})):
+                        ("anisotropic", synth.c3_anisotropic(), {}), ("depth_mask_sigma", synth.c3_depth(), {}),
+                        ("c2_depth_TS", synth.c2_depth(), {})):
+        if w.points != base.points:
+            x = torch.from_numpy(w.field(np.float32)).to(dev)
+            out = torch.empty_like(x)
         op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, w.nlev, n_img=w.n_img, qmode=w.qmode, device=dev,
                                   **kw)
         for _ in range(5):

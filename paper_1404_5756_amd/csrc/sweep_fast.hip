@@ -779,15 +779,15 @@ __global__ __launch_bounds__(64 * kXWaves, (LMAX <= 23 ? 3 : 2)) void k_rf3x_bat
 // ======================================================================
 constexpr int kYWin = 2;
 
-// One unit: planes pl0 .. pl0 + P-1 of one column block, each lane one column
-// of each plane.  phi: [2][16][64 * 9] in LDS (filled by y_planes); bsh: LDS
+// One unit: planes pl0, pl0 + pst, .., pl0 + (P-1) pst of one column block, each
+// lane one column of each plane.  phi: [2][16][64 * 9] in LDS (filled by y_planes); bsh: LDS
 // array of [2][16][2][64 * 3] floats, used here as [2][16][P][64 * 3].
 // KY: the local passes' K vectors [4 kinds][ny][nx][3].
 template <int L, bool ADJ, int P, bool END = false>
 __device__ __forceinline__ void y_unit(const float *in, float *out, const float4 *T, const float *KY,
                                        const uint64_t *LM, int nx_, int ny_, int blk, int pl0,
                                        float (*phi)[kYWaves][kYCols * 9], float *bsh_raw,
-                                       const float *ENDT = nullptr, float *xch = nullptr)
+                                       const float *ENDT = nullptr, float *xch = nullptr, int pst = 1)
 {
     auto bsh = reinterpret_cast<float (*)[kYWaves][P][kYCols * 3]>(bsh_raw);
     constexpr int LB = (L + 7) / 8;   // 8-row mask blocks per chunk
@@ -819,8 +819,8 @@ __device__ __forceinline__ void y_unit(const float *in, float *out, const float4
         Rsrc ri[P], ro[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            ri[p] = make_rsrc(in + (pl0 + p) * plane, (uint32_t)(plane * 4));
-            ro[p] = make_rsrc(out + (pl0 + p) * plane, (uint32_t)(plane * 4));
+            ri[p] = make_rsrc(in + (long)(pl0 + p * pst) * plane, (uint32_t)(plane * 4));
+            ro[p] = make_rsrc(out + (long)(pl0 + p * pst) * plane, (uint32_t)(plane * 4));
         }
         {
             // running row offset (a chain, so the compiler keeps one of them live)
@@ -1086,26 +1086,31 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y(const float *in, float
     y_planes<L, ADJ, END>(in, out, T, KY, LM, PHI, nx, ny, blk, pa, pb, (j + 2) % 3, phi, bsh, ENDT, xch);
 }
 
-// Depth-dependent tables (LevTabs): planes [pa, pb) of one column block one at a
-// time (plane p has level p % nlev), each with its level's tables; the level's
-// chunk transfer matrices go into LDS before each plane.
+// Depth-dependent tables (LevTabs): the units of one column block are (field
+// pair, level): the planes of fields 2q and 2q + 1 at one level share that
+// level's tables, so a lane carries both (one plane for the last of an odd field
+// count, or when L > 45).  A workgroup takes units [ua, ub) of its column block;
+// the level's chunk transfer matrices go into LDS before each unit.
 template <int L, bool ADJ, bool END>
 __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_lev(const float *in, float *out, const float4 *T,
                                                              const float *KY, const uint64_t *__restrict__ LM,
                                                              const float *__restrict__ PHI, int nx, int ny,
-                                                             int nplanes, int nblk, int nslot, LevTabs S,
-                                                             const float *__restrict__ ENDT)
+                                                             int nfields, int nunits, int nblk, int nslot,
+                                                             LevTabs S, const float *__restrict__ ENDT)
 {
+    constexpr int PM = y_planes_per_lane(L);
     __shared__ float phi[2][kYWaves][kYCols * 9];
     __shared__ float bsh[2 * kYWaves * 2 * kYCols * 3];
     __shared__ float xch[END ? kYWaves * 2 * 2 * kYCols : 1];
     const int bid = blockIdx.x, xcd = bid & 7, slot = bid >> 3;
     const int blk = (slot / nslot) * 8 + xcd, j = slot % nslot;
     if (blk >= nblk) return;
-    const int pa = (int)((long)j * nplanes / nslot), pb = (int)((long)(j + 1) * nplanes / nslot);
+    const int ua = (int)((long)j * nunits / nslot), ub = (int)((long)(j + 1) * nunits / nslot);
     const int k0 = ADJ ? 2 : 0;
-    for (int p = pa; p < pb; ++p) {
-        const int lev = p % S.nlev;
+    for (int u = ua; u < ub; ++u) {
+        const int lev = u % S.nlev, f0 = (u / S.nlev) * PM;
+        const int p = f0 * S.nlev + lev;
+        const bool two = PM == 2 && f0 + 1 < nfields;
         const float *ph = PHI + lev * S.phi;
         for (int e = threadIdx.x; e < 2 * kYWaves * kYCols; e += 64 * kYWaves) {
             const int sw = e / (kYWaves * kYCols), rest = e % (kYWaves * kYCols);
@@ -1114,9 +1119,13 @@ __global__ __launch_bounds__(64 * kYWaves, 1) void k_rf3y_lev(const float *in, f
             for (int q = 0; q < 9; ++q) phi[sw][rest / kYCols][(rest % kYCols) * 9 + q] = src[q];
         }
         __syncthreads();
-        y_unit<L, ADJ, 1, END>(in, out, T + lev * S.t, KY + lev * S.ky, LM + lev * S.lm, nx, ny, blk, p, phi, bsh,
-                               END ? ENDT + lev * S.end : nullptr, xch);
-        __syncthreads();   // phi, bsh and xch are rewritten for the next plane
+        if (two)
+            y_unit<L, ADJ, PM, END>(in, out, T + lev * S.t, KY + lev * S.ky, LM + lev * S.lm, nx, ny, blk, p, phi,
+                                    bsh, END ? ENDT + lev * S.end : nullptr, xch, S.nlev);
+        else
+            y_unit<L, ADJ, 1, END>(in, out, T + lev * S.t, KY + lev * S.ky, LM + lev * S.lm, nx, ny, blk, p, phi,
+                                   bsh, END ? ENDT + lev * S.end : nullptr, xch);
+        __syncthreads();   // phi, bsh and xch are rewritten for the next unit
     }
 }
 
@@ -1460,28 +1469,31 @@ static hipError_t launch_y(const float *in, float *out, const float4 *T, const f
                            hipStream_t st)
 {
     static_assert(y_planes_per_lane(L) == 1 || y_planes_per_lane(L) == 2, "planes per lane");
-    // depth-dependent tables: one plane per unit
+    if (lv && (lv->nlev < 1 || nplanes % lv->nlev)) return hipErrorNotSupported;
+    // depth-dependent tables: units of (field pair, level), counted as one-plane units here
+    const int nfields = lv ? nplanes / lv->nlev : 0;
+    const int nunits = lv ? lv->nlev * ((nfields + y_planes_per_lane(L) - 1) / y_planes_per_lane(L)) : 0;
     const int PM = lv ? 1 : y_planes_per_lane(L);
+    const int nwork = lv ? nunits : nplanes;
     const int nblk = (nx + kYCols - 1) / kYCols;
     // slots (workgroups) per column block: one workgroup per CU at a time, so
     // minimise (rounds of workgroups) x (cost of the largest plane range)
     const int cus = cu_count(), nb8 = ((nblk + 7) / 8) * 8;
     int best = 1;
     double best_cost = -1;
-    for (int sl = 1; sl <= nplanes; ++sl) {
+    for (int sl = 1; sl <= nwork; ++sl) {
         const long rounds = ((long)nb8 * sl + cus - 1) / cus;
-        const double cost = rounds * y_range_cost((nplanes + sl - 1) / sl, PM);
+        const double cost = rounds * y_range_cost((nwork + sl - 1) / sl, PM);
         if (best_cost < 0 || cost < best_cost - 1e-9) { best_cost = cost; best = sl; }
     }
     const unsigned nb = (unsigned)(nb8 * best);
     if (lv) {
-        if (lv->nlev < 1) return hipErrorNotSupported;
         if (ENDT)
-            k_rf3y_lev<L, ADJ, true><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nplanes, nblk, best,
-                                                                  *lv, ENDT);
+            k_rf3y_lev<L, ADJ, true><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nfields, nunits,
+                                                                  nblk, best, *lv, ENDT);
         else
-            k_rf3y_lev<L, ADJ, false><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nplanes, nblk,
-                                                                   best, *lv, nullptr);
+            k_rf3y_lev<L, ADJ, false><<<nb, 64 * kYWaves, 0, st>>>(in, out, T, KY, LM, PHI, nx, ny, nfields, nunits,
+                                                                   nblk, best, *lv, nullptr);
         return hipGetLastError();
     }
     if (ENDT)

@@ -132,6 +132,21 @@ def c3_depth(nlev=50):
     return Workload("c3_depth_1440x720x50", nx, ny, nlev, 1, mask, sig, sig.copy(), seed=seed)
 
 
+def c2_depth(nlev=72):
+    """The C2 grid (T and S) with a depth-dependent mask and length scales (Sec. 4: the
+    regional model's bathymetry): level k thresholds C2's smoothed blob field at the land
+    fraction 0.40 + 0.25 k/(nlev-1), so land only grows downwards, and sigma is C2's field
+    times (1 - 0.3 k/(nlev-1))."""
+    seed = SEEDS["c2"]
+    nx, ny = 871, 253
+    z = gaussian_filter(_rng(seed, 0).standard_normal((ny, nx)), 8.0, mode="wrap")
+    fr = 0.40 + 0.25 * np.arange(nlev) / max(nlev - 1, 1)
+    mask = np.stack([(z > np.quantile(z, f)).astype(np.uint8) for f in fr])
+    s2 = 2.0 + 8.0 * smooth_noise(_rng(seed, 1), ny, nx, 20.0)
+    sig = np.stack([s2 * (1.0 - 0.3 * k / max(nlev - 1, 1)) for k in range(nlev)])
+    return Workload("c2_depth_871x253x72_T+S", nx, ny, nlev, 2, mask, sig, sig.copy(), seed=seed)
+
+
 def c4_batch(nitems=64):
     """64 grids with nx~U[128,1024], ny~U[128,768], nlev~U[1,75], land~U[0.1,0.5], sigma in [2, 8]."""
     seed = SEEDS["c4"]

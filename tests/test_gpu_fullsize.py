@@ -104,6 +104,28 @@ def test_c2_forward_and_adjoint_full(orc):
     assert ef < TOL32 and ea < TOL32
 
 
+def test_c2_depth_full(orc):
+    """C2 (T and S, 72 levels) with a depth-dependent mask and sigma: the per-level tiled
+    kernels with both fields of a level in one y unit; every point, field-wide and line by line."""
+    dev = torch.device("cuda:0")
+    w = synth.c2_depth()
+    xh = w.field(np.float32)
+    x = torch.from_numpy(xh).to(dev)
+    op = _op(w, dev)
+    f = op.apply(x)
+    a = op.adjoint(x)
+    torch.cuda.synchronize()
+    P = _problem(orc, w)
+    x64 = xh.astype(np.float64)
+    fr, ar = P.rf3(x64, threads=THREADS), P.rf3_adjoint(x64, threads=THREADS)
+    fg, ag = f.double().cpu().numpy(), a.double().cpu().numpy()
+    ef, ea = rel(fg, fr), rel(ag, ar)
+    lf, la = assert_lines(fg, fr, "C2 depth forward"), assert_lines(ag, ar, "C2 depth adjoint")
+    print(f"C2 depth: fwd rel L2 {ef:.3e}, adj rel L2 {ea:.3e}; worst line {lf:.3f} / {la:.3f} of allowance",
+          flush=True)
+    assert ef < TOL32 and ea < TOL32
+
+
 def test_c4_batch_full(orc):
     dev = torch.device("cuda:0")
     ws = synth.c4_batch()

@@ -168,7 +168,8 @@ int rf1_apply_xy_fused(const rf_grid *g, const void *coef, rf_prec prec, int32_t
  * The x rows and y column blocks of all items form one work list; it runs as
  * one y launch and at most four x launches (one per occupancy class of the x
  * tile sizes) per direction, for any number of items.  Items whose mask or sigma vary with
- * level (mask_nlev or sigma_nlev > 1) run the line-sequential path instead.
+ * level (mask_nlev or sigma_nlev > 1), or with flags set, are not in the work list: they are
+ * applied one by one, as rf3_apply_xy / rf3_adjoint_xy would.
  *
  * Two steps, so that the apply step can be captured into a hipGraph:
  *   1. rf3_batch_plan (host only, no HIP call) writes the work list into host

@@ -96,7 +96,8 @@ def bench_batch(torch, dev, args):
     res = {"grids": len(ws), "points": pts, "ms_fwd_adj": round(ms_b, 3),
            "gpoints_s": round(pts / (ms_b * 1e-3) / 1e9, 2), "ms_default_shape": round(ms_default, 3),
            "ms_autotuned": round(ms_tuned, 3), "ms_graph_replay": round(ms_graph, 3),
-           "tuning": {"x_groups_max": b.tuning[0], "y_planes": b.tuning[1]} if b.tuning else "default",
+           "tuning": {"x_groups_max": b.tuning[0], "y_planes": b.tuning[1], "x_one_launch": b.tuning[2]}
+           if b.tuning else "default",
            "ms_per_grid_calls": round(ms_i, 3), "speedup_vs_per_grid_calls": round(ms_i / ms_b, 3),
            "setup_s": round(setup, 1), "autotune_s": round(tune_s, 1)}
     del g, b, ops, xs, ys

@@ -167,7 +167,8 @@ int rf1_apply_xy_fused(const rf_grid *g, const void *coef, rf_prec prec, int32_t
  *
  * The x rows and y column blocks of all items form one work list; it runs as
  * one y launch and at most four x launches (one per occupancy class of the x
- * tile sizes) per direction, for any number of items.  Items whose mask or sigma vary with
+ * tile sizes; one with rf_batch_tuning.x_one_launch) per direction, for any
+ * number of items.  Items whose mask or sigma vary with
  * level (mask_nlev or sigma_nlev > 1), or with flags set, are not in the work list: they are
  * applied one by one, as rf3_apply_xy / rf3_adjoint_xy would.
  *
@@ -210,6 +211,9 @@ typedef struct {
     int32_t x_groups_max;   /* max workgroups sharing the planes of one x row, 1..64 (a power of two
                                is used: the largest not above it); default 8 */
     int32_t y_planes;       /* planes per y work unit (one workgroup), 1..4096; default 8 */
+    int32_t x_one_launch;   /* 0 (default): one x launch per occupancy class of the x tile sizes;
+                               1: all x units in one launch, sized (registers, LDS) for the largest
+                               class present */
 } rf_batch_tuning;
 
 size_t rf3_batch_plan_bytes_ex(const rf_batch_item *items, int32_t n, const rf_batch_tuning *t);

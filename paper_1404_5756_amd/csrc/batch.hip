@@ -26,17 +26,19 @@ constexpr int kYPlanesPerUnit = 8;
 constexpr int kXGroupsMax = 8;
 
 struct Tuning {
-    int x_groups_max, y_planes;
+    int x_groups_max, y_planes, x_one;
 };
 
 // the work-list shape: defaults for zero fields; false on values out of range
 bool tuning_of(const rf_batch_tuning *t, Tuning &o)
 {
-    o = Tuning{kXGroupsMax, kYPlanesPerUnit};
+    o = Tuning{kXGroupsMax, kYPlanesPerUnit, 0};
     if (!t) return true;
     if (t->x_groups_max < 0 || t->x_groups_max > 64 || t->y_planes < 0 || t->y_planes > 4096) return false;
+    if (t->x_one_launch != 0 && t->x_one_launch != 1) return false;
     if (t->x_groups_max) o.x_groups_max = t->x_groups_max;
     if (t->y_planes) o.y_planes = t->y_planes;
+    o.x_one = t->x_one_launch;
     return true;
 }
 
@@ -236,15 +238,19 @@ extern "C" int rf3_apply_batch_ex(const rf_batch_item *items, int32_t n, const r
         if (dir == 1) {
             e = fast_rf3_y_batch(E, U + y_off, (int)P.units.size() - y_off, adj, pass == 1, st);
         } else {
-            // consecutive x groups of one occupancy class make one launch
+            // consecutive x groups of one occupancy class make one launch; with
+            // x_one, all x groups (contiguous, largest tiles first) make one launch
+            // of the largest class present
             for (size_t k = 0; k < P.groups.size() && e == hipSuccess;) {
                 const Group &gr = P.groups[k];
                 if (gr.dir != 0) { ++k; continue; }
                 const int cls = x_batch_class(gr.L);
                 int count = 0;
-                for (; k < P.groups.size() && P.groups[k].dir == 0 && x_batch_class(P.groups[k].L) == cls; ++k)
+                for (; k < P.groups.size() && P.groups[k].dir == 0 &&
+                       (tu.x_one || x_batch_class(P.groups[k].L) == cls);
+                     ++k)
                     count += P.groups[k].count;
-                e = fast_rf3_x_batch(E, U + gr.offset, count, cls, adj, pass == 1, st);
+                e = fast_rf3_x_batch(E, U + gr.offset, count, cls, adj, pass == 1, tu.x_one != 0, st);
             }
         }
         if (e != hipSuccess) return RF_E_HIP;

@@ -734,11 +734,13 @@ __global__ __launch_bounds__(64 * kXWaves, 2) void k_rf3x_lev(const float *in, f
 // which the smaller tiles of the class fit without losing occupancy.
 #define RF_XB_UNIT(Lv)                                                                                    \
     case Lv:                                                                                              \
-        if constexpr (x_batch_class(Lv) == LMAX)                                                          \
+        if constexpr (ALL ? x_batch_class(Lv) <= LMAX : x_batch_class(Lv) == LMAX)                        \
             x_rows<Lv, ADJ>(in, out, T, LM, PHI, nx, ny, nplanes, row, grp, groups, K, stg);              \
         break;
 
-template <int LMAX, bool ADJ>
+// ALL: the launch also serves the units of every smaller class (one x launch
+// for the whole work list)
+template <int LMAX, bool ADJ, bool ALL>
 __global__ __launch_bounds__(64 * kXWaves, (LMAX <= 23 ? 3 : 2)) void k_rf3x_batch(
     const BatchEntry *__restrict__ E, const BatchUnit *__restrict__ U, int src_out)
 {
@@ -1539,26 +1541,31 @@ hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float 
     }
 }
 
+template <int LMAX, bool ALL>
+static void launch_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, bool adj, bool src_out,
+                           hipStream_t st)
+{
+    if (adj) k_rf3x_batch<LMAX, true, ALL><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+    else k_rf3x_batch<LMAX, false, ALL><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+}
+
 hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int cls, bool adj, bool src_out,
-                            hipStream_t st)
+                            bool all_classes, hipStream_t st)
 {
     if (nunits <= 0) return hipSuccess;
     switch (cls) {
-    case 3:
-        if (adj) k_rf3x_batch<3, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
-        else k_rf3x_batch<3, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
-        break;
+    case 3: launch_x_batch<3, false>(E, U, nunits, adj, src_out, st); break;   // the smallest class: no others
     case 11:
-        if (adj) k_rf3x_batch<11, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
-        else k_rf3x_batch<11, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        if (all_classes) launch_x_batch<11, true>(E, U, nunits, adj, src_out, st);
+        else launch_x_batch<11, false>(E, U, nunits, adj, src_out, st);
         break;
     case 23:
-        if (adj) k_rf3x_batch<23, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
-        else k_rf3x_batch<23, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        if (all_classes) launch_x_batch<23, true>(E, U, nunits, adj, src_out, st);
+        else launch_x_batch<23, false>(E, U, nunits, adj, src_out, st);
         break;
     case 33:
-        if (adj) k_rf3x_batch<33, true><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
-        else k_rf3x_batch<33, false><<<nunits, 64 * kXWaves, 0, st>>>(E, U, src_out);
+        if (all_classes) launch_x_batch<33, true>(E, U, nunits, adj, src_out, st);
+        else launch_x_batch<33, false>(E, U, nunits, adj, src_out, st);
         break;
     default: return hipErrorNotSupported;
     }

@@ -36,10 +36,11 @@ hipError_t fast_rf3_y(const float *in, float *out, const float4 *T, const float 
                       const float *PHI, int ly, int nx, int ny, int nplanes, bool adj, const float *ENDT,
                       const LevTabs *lv, hipStream_t st);
 // batched forms over a work list: x units of one launch share the occupancy
-// class of their tile size (x_batch_class), a y launch takes units of any tile
-// size; each unit's tile size follows from its item's nx or ny
+// class of their tile size (x_batch_class), or (all_classes) have any class up
+// to cls; a y launch takes units of any tile size; each unit's tile size follows
+// from its item's nx or ny
 hipError_t fast_rf3_x_batch(const BatchEntry *E, const BatchUnit *U, int nunits, int cls, bool adj, bool src_out,
-                            hipStream_t st);
+                            bool all_classes, hipStream_t st);
 hipError_t fast_rf3_y_batch(const BatchEntry *E, const BatchUnit *U, int nunits, bool adj, bool src_out,
                             hipStream_t st);
 int x_groups(int ny, int nplanes, int gmax);

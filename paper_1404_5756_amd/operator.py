@@ -116,12 +116,12 @@ class Batch:
     items: [(HorizontalCovariance, x, y)] with x, y FP32 device tensors
     [nfields][op.nlev][ny][nx] (y may be x).  The work list is built once here
     and kept on the device; build a new Batch when any tensor changes.
-    tuning: None (default work-list shape) or (x_groups_max, y_planes), see
-    rf_batch_tuning; autotune() picks one by timing.
+    tuning: None (default work-list shape) or (x_groups_max, y_planes[, x_one_launch]),
+    see rf_batch_tuning; autotune() picks one by timing.
     """
 
-    # candidate work-list shapes tried by autotune(): (x_groups_max, y_planes)
-    CANDIDATES = tuple((xg, yp) for xg in (1, 2, 4, 8, 16) for yp in (1, 2, 3, 4, 6, 8, 16))
+    # candidate work-list shapes tried by autotune(): (x_groups_max, y_planes, x_one_launch)
+    CANDIDATES = tuple((xg, yp, one) for one in (0, 1) for xg in (1, 2, 4, 8, 16) for yp in (1, 2, 3, 4, 6, 8, 16))
 
     def __init__(self, items, device=None, tuning=None):
         self._items = []
@@ -138,8 +138,13 @@ class Batch:
         self.device = device if device is not None else self._items[0][2].device
         self._set_tuning(tuning)
 
+    @staticmethod
+    def _norm(tuning):
+        """(x_groups_max, y_planes, x_one_launch) of a 2- or 3-tuple, or None."""
+        return None if tuning is None else (int(tuning[0]), int(tuning[1]), int(tuning[2]) if len(tuning) > 2 else 0)
+
     def _set_tuning(self, tuning):
-        self.tuning = None if tuning is None else (int(tuning[0]), int(tuning[1]))
+        self.tuning = self._norm(tuning)
         host = rf3.rf3_batch_plan(self._items, self.tuning)
         # torch's caching allocator returns 512-byte aligned blocks
         self.plan = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(self.device)
@@ -168,7 +173,8 @@ class Batch:
         """Time forward + adjoint for each candidate work-list shape on these items
         and keep the fastest.  The batch is applied repeatedly: the items' outputs
         (and inputs, for items applied in place) are overwritten.  Returns
-        {shape: ms} with the default shape under the key None.  With cache, a batch
+        {shape: ms}, shapes as (x_groups_max, y_planes, x_one_launch), with the
+        default shape under the key None.  With cache, a batch
         whose signature() was tuned before in this process takes that shape without
         timing (and returns {}); results do not depend on the shape (bitwise)."""
         key = self.signature() if cache and candidates is None else None
@@ -177,7 +183,7 @@ class Batch:
             return {}
         stream = torch.cuda.current_stream(self.device)
         times = {}
-        for t in [None] + list(candidates if candidates is not None else self.CANDIDATES):
+        for t in [None] + [self._norm(c) for c in (candidates if candidates is not None else self.CANDIDATES)]:
             self._set_tuning(t)
             self.apply(False)
             self.apply(True)

@@ -37,10 +37,11 @@ class rf_batch_item(ctypes.Structure):
 
 
 class rf_batch_tuning(ctypes.Structure):
-    _fields_ = [("x_groups_max", ctypes.c_int32), ("y_planes", ctypes.c_int32)]
+    _fields_ = [("x_groups_max", ctypes.c_int32), ("y_planes", ctypes.c_int32), ("x_one_launch", ctypes.c_int32)]
 
     def __repr__(self):
-        return f"rf_batch_tuning(x_groups_max={self.x_groups_max}, y_planes={self.y_planes})"
+        return (f"rf_batch_tuning(x_groups_max={self.x_groups_max}, y_planes={self.y_planes}, "
+                f"x_one_launch={self.x_one_launch})")
 
 
 class RFError(RuntimeError):
@@ -201,11 +202,11 @@ def _items(items):
 
 
 def _tuning(tuning):
-    """None (defaults), an rf_batch_tuning, or a (x_groups_max, y_planes) pair."""
+    """None (defaults), an rf_batch_tuning, or (x_groups_max, y_planes[, x_one_launch])."""
     if tuning is None or isinstance(tuning, rf_batch_tuning):
         return tuning
-    xg, yp = tuning
-    return rf_batch_tuning(int(xg), int(yp))
+    xg, yp, *rest = tuning
+    return rf_batch_tuning(int(xg), int(yp), int(rest[0]) if rest else 0)
 
 
 def _tptr(t):

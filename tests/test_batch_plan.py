@@ -147,11 +147,13 @@ def test_tuning_shapes_the_work_list():
 def test_tuning_out_of_range_is_refused():
     g = rf3.make_grid(64, 64, 2)
     items = [(g, FAKE, FAKE + (1 << 36), FAKE + (1 << 36) + (1 << 31), 1)]
-    for t in ((-1, 0), (0, -1), (65, 0), (0, 4097)):
+    for t in ((-1, 0), (0, -1), (65, 0), (0, 4097), (0, 0, 2), (0, 0, -1)):
         assert rf3.rf3_batch_plan_bytes(items, t) == 0
         with pytest.raises(rf3.RFError):
             rf3.rf3_batch_plan(items, t)
     assert rf3.rf3_batch_plan_bytes(items, (0, 0)) == rf3.rf3_batch_plan_bytes(items)
+    # one x launch changes the launches, not the work list
+    assert rf3.rf3_batch_plan(items, (0, 0, 1)) == rf3.rf3_batch_plan(items)
     arr, _keep = rf3._items(items)
     bad = rf3.rf_batch_tuning(0, -3)
     assert rf3.lib().rf3_apply_batch_ex(arr, 1, ctypes.byref(bad), rf3.RF_FP32, 0, ctypes.c_void_p(FAKE), 256,

@@ -126,7 +126,7 @@ def _batch_items(ops, xs):
     return items, outs
 
 
-@pytest.mark.parametrize("tuning", [(1, 1), (2, 3), (16, 2), (64, 64)])
+@pytest.mark.parametrize("tuning", [(1, 1), (2, 3), (16, 2), (64, 64), (1, 4, 1), (8, 8, 1)])
 def test_batch_tuning_is_bitwise_neutral(batch_setup, tuning):
     """Any work-list shape gives exactly the default result (same kernels per line)."""
     ws, ops, xs = batch_setup
@@ -144,8 +144,8 @@ def test_batch_autotune(batch_setup):
     ws, ops, xs = batch_setup
     items, outs = _batch_items(ops, xs)
     b = Batch(items)
-    times = b.autotune(candidates=[(2, 2), (8, 16)], reps=1)
-    assert set(times) == {None, (2, 2), (8, 16)} and all(t > 0 for t in times.values())
+    times = b.autotune(candidates=[(2, 2), (8, 16, 1)], reps=1)
+    assert set(times) == {None, (2, 2, 0), (8, 16, 1)} and all(t > 0 for t in times.values())
     assert b.tuning == min(times, key=times.get)
     # the tuned batch still computes V_H: rerun on fresh copies of the inputs
     items2, outs2 = _batch_items(ops, xs)

@@ -169,12 +169,15 @@ class Batch:
                               for g, _c, _x, _y, nf in self._items))
         return (arch, props.multi_processor_count, shapes)
 
-    def autotune(self, candidates=None, reps=3, cache=True):
+    def autotune(self, candidates=None, reps=3, cache=True, finalists=4, rounds=3):
         """Time forward + adjoint for each candidate work-list shape on these items
         and keep the fastest.  The batch is applied repeatedly: the items' outputs
         (and inputs, for items applied in place) are overwritten.  Returns
         {shape: ms}, shapes as (x_groups_max, y_planes, x_one_launch), with the
-        default shape under the key None.  With cache, a batch
+        default shape under the key None.  Shapes a few percent apart are within
+        the timing noise, so the fastest `finalists` shapes and the default are
+        timed again in `rounds` interleaved rounds, and the best mean over those
+        rounds (their entries in the result) wins.  With cache, a batch
         whose signature() was tuned before in this process takes that shape without
         timing (and returns {}); results do not depend on the shape (bitwise)."""
         key = self.signature() if cache and candidates is None else None
@@ -182,8 +185,8 @@ class Batch:
             self._set_tuning(Batch._tuned[key])
             return {}
         stream = torch.cuda.current_stream(self.device)
-        times = {}
-        for t in [None] + [self._norm(c) for c in (candidates if candidates is not None else self.CANDIDATES)]:
+
+        def timed(t):
             self._set_tuning(t)
             self.apply(False)
             self.apply(True)
@@ -194,8 +197,21 @@ class Batch:
                 self.apply(True)
             b.record(stream)
             b.synchronize()
-            times[t] = a.elapsed_time(b) / reps
-        best = min(times, key=times.get)
+            return a.elapsed_time(b) / reps
+
+        times = {}
+        for t in [None] + [self._norm(c) for c in (candidates if candidates is not None else self.CANDIDATES)]:
+            times[t] = timed(t)
+        final = sorted(times, key=times.get)[:finalists]
+        if None not in final:
+            final.append(None)
+        acc = dict.fromkeys(final, 0.0)
+        for _ in range(rounds):
+            for t in final:
+                acc[t] += timed(t)
+        for t in final:
+            times[t] = acc[t] / rounds
+        best = min(final, key=times.get)
         self._set_tuning(best)
         if key is not None:
             Batch._tuned[key] = best

@@ -367,12 +367,15 @@ def main():
         ms_f64 = timed_rf1(lambda: op.rf1_fused(x64, K=5, out=o64))
         o32 = torch.empty_like(x)
         ms_f32 = timed_rf1(lambda: op.rf1_fused(x, K=5, out=o32))
+        # the FP64 3rd-RF (line-sequential kernels, the printed form), forward + adjoint
+        ms_rf3_64 = timed_rf1(lambda: (op.apply(x64, out=o64), op.adjoint(x64, out=o64)), 3)
         rf1 = {"ms": round(ms_rf1, 3), "gpoints_s": round(pts / (ms_rf1 * 1e-3) / 1e9, 2),
                "speedup_rf3_fp32_fwd_vs_rf1_fp64_k5": round(ms_rf1 / ms_fwd, 2),
                "fused_fp64_ms": round(ms_f64, 3), "speedup_rf3_fp32_fwd_vs_fused_rf1_fp64_k5": round(ms_f64 / ms_fwd, 2),
-               "fused_fp32_ms": round(ms_f32, 3), "speedup_rf3_fp32_fwd_vs_fused_rf1_fp32_k5": round(ms_f32 / ms_fwd, 2)}
+               "fused_fp32_ms": round(ms_f32, 3), "speedup_rf3_fp32_fwd_vs_fused_rf1_fp32_k5": round(ms_f32 / ms_fwd, 2),
+               "rf3_fp64_fwd_adj_ms": round(ms_rf3_64, 3)}
         log(f"1st-RF K=5: plain FP64 {ms_rf1:.3f} ms, fused FP64 {ms_f64:.3f} ms, fused FP32 {ms_f32:.3f} ms; "
-            f"3rd-RF FP32 forward {ms_fwd:.3f} ms")
+            f"3rd-RF FP32 forward {ms_fwd:.3f} ms; 3rd-RF FP64 forward + adjoint {ms_rf3_64:.3f} ms")
         rf1["k_frontier"] = k_frontier(torch, dev, w, x, ms_fwd, args)
         del x64, o64, o32
 

@@ -6,8 +6,9 @@ lane masks and scan tables.  Each case runs the tiled kernels (per-level tables)
 and the line-sequential ones (RF3_SEQUENTIAL=1) against the FP64 oracle,
 field-wide (relative L2 1e-5) and line by line, and against each other line by
 line; forward and adjoint, several fields, tile sizes x 23 / y 45, x 33 / y 56 and
-x 1 / y 1, mask-only and sigma-only depth dependence, and a call on fewer levels
-than the grid holds (it takes the first levels' tables).
+x 1 / y 1, mask-only and sigma-only depth dependence, a call on fewer levels
+than the grid holds (it takes the first levels' tables), and exact ends with
+two fields.
 """
 import numpy as np
 import pytest
@@ -66,3 +67,38 @@ def test_depth_tables(c, orc, monkeypatch):
             print(f"  levels {nl} {name}: rel {e:.2e} (sequential {es:.2e}); worst line {lr:.3f} / {ls:.3f} "
                   f"(tiled vs sequential {lt:.3f}) of allowance", flush=True)
             assert e <= TOL32 and es <= TOL32
+
+
+# exact ends with depth-dependent tables: the end maps per level, and (two fields) the y units
+# that pair the fields of a level exchange the end corrections of both planes; per-line bound
+# of the exact-end FP32 paths
+TOL_LINE_END = 3e-5
+ECASES = [
+    # seed, ny, nx, nlev, nfields, 3-D mask, 3-D sigma
+    (65, 120, 700, 3, 2, True, True),
+    (66, 720, 1440, 2, 2, True, False),
+]
+
+
+@pytest.mark.parametrize("c", ECASES, ids=lambda c: f"depth_end_s{c[0]}_{c[2]}x{c[1]}x{c[3]}_f{c[4]}")
+def test_depth_tables_exact_ends(c, orc, monkeypatch):
+    seed, ny, nx, nlev, nf, m3, s3 = c
+    w = synth.random_case(seed, ny, nx, nlev, 0.3, 4, (1.5, 12.0), 3.0, "fit", m3, s3)
+    print(f"depth exact-ends case {w.name} nfields={nf}", flush=True)
+    op = HorizontalCovariance(w.mask, w.sigma_x, w.sigma_y, nlev, n_img=w.n_img, qmode=w.qmode, k1=5,
+                              exact_ends=True)
+    P = orc.Problem(w.mask, w.sigma_x, w.sigma_y, n_img=w.n_img, qmode=orc.QMODES[w.qmode], k1=5,
+                    flags=orc.EXACT_ENDS)
+    x = w.field(np.float32, nfields=nf)
+    for name, fn, ref in (("forward", op.apply, P.rf3), ("adjoint", op.adjoint, P.rf3_adjoint)):
+        r = ref(x.astype(np.float64), threads=16)
+        monkeypatch.delenv("RF3_SEQUENTIAL", raising=False)
+        got = fn(torch.from_numpy(x).cuda()).cpu().numpy()
+        monkeypatch.setenv("RF3_SEQUENTIAL", "1")
+        seq = fn(torch.from_numpy(x).cuda()).cpu().numpy()
+        monkeypatch.delenv("RF3_SEQUENTIAL")
+        e = rel(got, r)
+        lr = assert_lines(got, r, f"{w.name} exact ends tiled {name}", TOL_LINE_END)
+        lt = assert_lines(got, seq, f"{w.name} exact ends tiled vs sequential {name}", TOL_LINE_END)
+        print(f"  {name}: rel {e:.2e}; worst line {lr:.3f} (tiled vs sequential {lt:.3f}) of allowance", flush=True)
+        assert e <= TOL32

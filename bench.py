@@ -419,6 +419,42 @@ def main():
         cpu["one_thread"] = {"value": round(w.nx * w.ny * n1 / t1s / 1e9, 5), "unit": "Gpoints/s",
                              "seconds": round(t1s, 2), "sample": f"fwd+adj V_H of {n1} levels, 1 thread"}
         log(f"cpu oracle on 1 thread: {t1s:.2f} s for {n1} levels")
+        # the oracle's plain 1st-RF (K = 5) on the same sample, and the oracle's 3rd-RF on C2 (T and S)
+        t0 = time.time()
+        P.rf1(xs, K=5, threads=threads)
+        t_rf1 = time.time() - t0
+        cpu["rf1_k5"] = {"value": round(sample_pts / t_rf1 / 1e9, 5), "unit": "Gpoints/s", "seconds": round(t_rf1, 2),
+                         "sample": f"1st-RF K = 5, x then y, of {nl} levels, {threads} threads"}
+        from paper_1404_5756_amd import synth
+        w2 = synth.c2_regional()
+        P2 = oracle.Problem(w2.mask, w2.sigma_x, w2.sigma_y, n_img=w2.n_img, qmode=oracle.QMODES[w2.qmode], k1=5)
+        x2 = w2.field(np.float64)
+        t0 = time.time()
+        P2.rf3(x2, threads=threads)
+        P2.rf3_adjoint(x2, threads=threads)
+        t_c2 = time.time() - t0
+        cpu["c2"] = {"value": round(w2.points / t_c2 / 1e9, 5), "unit": "Gpoints/s", "seconds": round(t_c2, 2),
+                     "sample": f"fwd+adj V_H of C2 (871 x 253 x 72, T and S), {threads} threads"}
+        # one oracle CG iteration of C5 (the C3 grid, 200k observations), after the initial residual
+        import oracle.var3d as ov
+        lev, ox, oy = synth.c5_observations(w)
+        idx, wt = ov.obs_weights(w.nx, w.ny, lev, ox, oy)
+        shape = (1, w.nlev, w.ny, w.nx)
+        n = int(np.prod(shape))
+        yobs = np.random.default_rng(5).standard_normal(len(lev))
+        t0 = time.time()
+        ov.cg(lambda v: P.rf3(v.reshape(shape), threads=threads).ravel(),
+              lambda v: P.rf3_adjoint(v.reshape(shape), threads=threads).ravel(), idx, wt, yobs, 4.0, n, 0)
+        t_r0 = time.time() - t0
+        t0 = time.time()
+        ov.cg(lambda v: P.rf3(v.reshape(shape), threads=threads).ravel(),
+              lambda v: P.rf3_adjoint(v.reshape(shape), threads=threads).ravel(), idx, wt, yobs, 4.0, n, 1)
+        t_it = time.time() - t0 - t_r0
+        cpu["c5_cg_iteration"] = {"seconds": round(t_it, 2),
+                                  "sample": f"one CG iteration (V, H, H^T, V^T, vector updates) of C5, {threads} threads"}
+        log(f"cpu oracle: 1st-RF K=5 {t_rf1:.2f} s for {nl} levels; C2 fwd+adj {t_c2:.2f} s; "
+            f"one C5 CG iteration {t_it:.2f} s")
+        del x2, P2
         op.apply(x, out=out_f)
         op.adjoint(x, out=out_a)
         torch.cuda.synchronize()

@@ -158,3 +158,21 @@ def test_tuning_out_of_range_is_refused():
     bad = rf3.rf_batch_tuning(0, -3)
     assert rf3.lib().rf3_apply_batch_ex(arr, 1, ctypes.byref(bad), rf3.RF_FP32, 0, ctypes.c_void_p(FAKE), 256,
                                         None) == rf3.RF_E_ARG
+
+
+def test_tuning_struct_matches_the_header():
+    """rf_batch_tuning is three int32 fields (x_groups_max, y_planes, x_one_launch) in
+    include/rf3.h; the binding's struct must have the same size and order, and a
+    (x_groups_max, y_planes) pair means x_one_launch = 0."""
+    import re
+    from pathlib import Path
+    hdr = (Path(__file__).resolve().parents[1] / "include" / "rf3.h").read_text()
+    body = hdr[:hdr.index("} rf_batch_tuning;")]
+    body = body[body.rindex("typedef struct {"):]
+    fields = re.findall(r"int32_t\s+(\w+);", body)
+    assert fields == [f for f, _ in rf3.rf_batch_tuning._fields_]
+    assert ctypes.sizeof(rf3.rf_batch_tuning) == 4 * len(fields)
+    t = rf3._tuning((4, 6))
+    assert (t.x_groups_max, t.y_planes, t.x_one_launch) == (4, 6, 0)
+    t = rf3._tuning((1, 2, 1))
+    assert (t.x_groups_max, t.y_planes, t.x_one_launch) == (1, 2, 1)
